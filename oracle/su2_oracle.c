@@ -1,0 +1,523 @@
+/*
+ * su2_oracle.c -- plain FP64 CPU reference (TEST INFRASTRUCTURE ONLY; see
+ * su2_oracle.h).  Deliberately simple: natural site order, coordinates
+ * recomputed for every neighbour, no blocking, no fusion.  The only
+ * parallelism is an OpenMP loop over the sites of one checkerboard class,
+ * whose links are mutually independent, so the result does not depend on
+ * the thread count.
+ *
+ * Pins (what fixes each function other than itself):
+ *  - or_philox4x32_10: raw outputs against PyTorch's header-only host Philox
+ *    engine (a separately written implementation of the same published
+ *    generator), plus uniformity statistics;
+ *  - or_u01_f64 / or_u01_f32: exhaustive edge values (closed form);
+ *  - or_qmul / or_qdag: numpy complex 2x2 matrix products;
+ *  - or_staple: brute-force change of the total Wilson action;
+ *  - or_init_hot: Haar moments and the Haar density of a0 (KS);
+ *  - heat bath: conditional law of one link (KS against the exact density,
+ *    mean against a ratio of Bessel functions), probability-integral
+ *    transform at equilibrium, strong- and weak-coupling limits;
+ *  - overrelaxation: action conservation and involution;
+ *  - observables: cold start = 1, gauge invariance, Z2 centre symmetry.
+ */
+#include "su2_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const double OR_PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, Salmon et al. SC'11 (2011): ten rounds of two 32x32->64    */
+/* multiplications with the round multipliers below, the key bumped by the  */
+/* Weyl constants between rounds.                                            */
+/* ------------------------------------------------------------------------ */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[2];
+        uint32_t next[4];
+        next[0] = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        next[1] = (uint32_t)p1;
+        next[2] = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        next[3] = (uint32_t)p0;
+        memcpy(c, next, sizeof c);
+    }
+    memcpy(out, c, sizeof c);
+}
+
+/* Uniform in the open interval (0,1): the top 52 bits of the 64-bit word
+ * (r_even, r_odd) plus one half, times 2^-52. */
+double or_u01_f64(uint32_t r_even, uint32_t r_odd)
+{
+    uint64_t w = ((uint64_t)r_even << 32) | (uint64_t)r_odd;
+    uint64_t m = w >> 12;
+    return ((double)m + 0.5) * 0x1p-52;
+}
+
+/* Single-precision uniform from the top 23 bits of r_even, so that it is the
+ * FP64 uniform of the same pair rounded to 23 bits. */
+float or_u01_f32(uint32_t r_even)
+{
+    uint32_t m = r_even >> 9;
+    return ((float)m + 0.5f) * 0x1p-23f;
+}
+
+/* Two FP64 uniforms from one Philox call at counter (site, c1, c2, c3). */
+static void draw2(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                  double *ua, double *ub)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    or_philox4x32_10(ctr, key, r);
+    *ua = or_u01_f64(r[0], r[1]);
+    *ub = or_u01_f64(r[2], r[3]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quaternion form of SU(2): U = a0 + i a.sigma, so that                      */
+/* (a0,a)(b0,b) = (a0 b0 - a.b, a0 b + b0 a - a x b), U^dagger = (a0, -a),  */
+/* and half the trace of U is a0.                                            */
+/* ------------------------------------------------------------------------ */
+void or_qmul(const double a[4], const double b[4], double out[4])
+{
+    double r0 = a[0] * b[0] - (a[1] * b[1] + a[2] * b[2] + a[3] * b[3]);
+    double r1 = a[0] * b[1] + b[0] * a[1] - (a[2] * b[3] - a[3] * b[2]);
+    double r2 = a[0] * b[2] + b[0] * a[2] - (a[3] * b[1] - a[1] * b[3]);
+    double r3 = a[0] * b[3] + b[0] * a[3] - (a[1] * b[2] - a[2] * b[1]);
+    out[0] = r0;
+    out[1] = r1;
+    out[2] = r2;
+    out[3] = r3;
+}
+
+void or_qdag(const double a[4], double out[4])
+{
+    out[0] = a[0];
+    out[1] = -a[1];
+    out[2] = -a[2];
+    out[3] = -a[3];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry: periodic 4-D lattice, x fastest.                                */
+/* ------------------------------------------------------------------------ */
+int64_t or_volume(const int n[4])
+{
+    return (int64_t)n[0] * n[1] * n[2] * n[3];
+}
+
+static void coords(const int n[4], int64_t site, int c[4])
+{
+    for (int d = 0; d < 4; ++d) {
+        c[d] = (int)(site % n[d]);
+        site /= n[d];
+    }
+}
+
+static int64_t site_of(const int n[4], const int c[4])
+{
+    return c[0] + (int64_t)n[0] * (c[1] + (int64_t)n[1] * (c[2] + (int64_t)n[2] * c[3]));
+}
+
+int64_t or_neighbor(const int n[4], int64_t site, int dir, int step)
+{
+    int c[4];
+    coords(n, site, c);
+    c[dir] = ((c[dir] + step) % n[dir] + n[dir]) % n[dir];
+    return site_of(n, c);
+}
+
+int or_parity(const int n[4], int64_t site)
+{
+    int c[4];
+    coords(n, site, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+static const double *link(const double *U, int64_t site, int mu)
+{
+    return U + (site * 4 + mu) * 4;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Staple sum for link U_mu(x): the Wilson action of the plaquettes holding  */
+/* this link is -(beta/2) Tr(U_mu(x) V) + const with                        */
+/*   V = sum_{nu != mu} [ U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+                  */
+/*                      + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu) ].         */
+/* ------------------------------------------------------------------------ */
+void or_staple(const int n[4], const double *U, int64_t site, int mu, double V[4])
+{
+    V[0] = V[1] = V[2] = V[3] = 0.0;
+    int64_t xp = or_neighbor(n, site, mu, +1);
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu)
+            continue;
+        double t1[4], t2[4], d[4], s[4];
+        /* upper: U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ */
+        int64_t xn = or_neighbor(n, site, nu, +1);
+        or_qdag(link(U, xn, mu), d);
+        or_qmul(link(U, xp, nu), d, t1);
+        or_qdag(link(U, site, nu), d);
+        or_qmul(t1, d, s);
+        for (int k = 0; k < 4; ++k)
+            V[k] += s[k];
+        /* lower: U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu) */
+        int64_t xm = or_neighbor(n, site, nu, -1);
+        int64_t xpm = or_neighbor(n, xp, nu, -1);
+        double d2[4];
+        or_qdag(link(U, xpm, nu), d);
+        or_qdag(link(U, xm, mu), d2);
+        or_qmul(d, d2, t2);
+        or_qmul(t2, link(U, xm, nu), s);
+        for (int k = 0; k < 4; ++k)
+            V[k] += s[k];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Starts (Sec. 2.1: "random SU(2) matrix initialization").                  */
+/* ------------------------------------------------------------------------ */
+void or_init_cold(const int n[4], double *U)
+{
+    int64_t nl = or_volume(n) * 4;
+    for (int64_t l = 0; l < nl; ++l) {
+        U[4 * l + 0] = 1.0;
+        U[4 * l + 1] = 0.0;
+        U[4 * l + 2] = 0.0;
+        U[4 * l + 3] = 0.0;
+    }
+}
+
+/* A Haar-random SU(2) element: four independent standard normals by the
+ * Box-Muller transform, normalised onto the unit 3-sphere. */
+static void haar_from_counter(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, double q[4])
+{
+    double u1, u2, u3, u4;
+    draw2(seed, c0, c1, c2, 0u, &u1, &u2);
+    draw2(seed, c0, c1, c2, 1u, &u3, &u4);
+    double r1 = sqrt(-2.0 * log(u1));
+    double r2 = sqrt(-2.0 * log(u3));
+    double g[4] = {r1 * cos(2.0 * OR_PI * u2), r1 * sin(2.0 * OR_PI * u2),
+                   r2 * cos(2.0 * OR_PI * u4), r2 * sin(2.0 * OR_PI * u4)};
+    double norm = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + g[3] * g[3]);
+    for (int k = 0; k < 4; ++k)
+        q[k] = g[k] / norm;
+}
+
+void or_init_hot(const int n[4], double *U, uint64_t seed, uint32_t lattice_id)
+{
+    int64_t vol = or_volume(n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < vol; ++i)
+        for (int mu = 0; mu < 4; ++mu)
+            haar_from_counter(seed, (uint32_t)i, (uint32_t)(mu + 4 * 0 + 16 * lattice_id), 0u,
+                              U + (i * 4 + mu) * 4);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Heat bath for one link.  The link's conditional law is proportional to    */
+/* exp((beta/2) Tr(U V)) dU.  With k = |V| and Vhat = V/k, W = U Vhat has    */
+/* density ~ exp(alpha w0) dHaar(W), alpha = beta k, i.e. w0 has density     */
+/* ~ sqrt(1 - w0^2) exp(alpha w0) on [-1,1] and (w1,w2,w3) is isotropic with */
+/* length sqrt(1 - w0^2).  Then U = W Vhat^dagger.                           */
+/*   alpha >= 2: Kennedy-Pendleton; alpha < 2: Creutz.                       */
+/* ------------------------------------------------------------------------ */
+static uint32_t heatbath_link(double Ulink[4], const double V[4], double beta, uint64_t seed,
+                              uint32_t site, uint32_t c1, uint32_t sweep)
+{
+    double k = sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2] + V[3] * V[3]);
+    if (!isfinite(k))
+        return OR_FLAG_NONFINITE;
+    double Vhat[4] = {1.0, 0.0, 0.0, 0.0};
+    if (k > 0.0)
+        for (int j = 0; j < 4; ++j)
+            Vhat[j] = V[j] / k;
+    double alpha = beta * k;
+
+    double x0 = 0.0, xlen = 0.0;
+    int accepted = 0;
+    for (uint32_t a = 0; a < OR_MAX_ATTEMPTS && !accepted; ++a) {
+        if (alpha >= 2.0) {
+            /* Kennedy-Pendleton: lambda^2 from two exponentials, accept with
+             * probability sqrt(1 - lambda^2), x0 = 1 - 2 lambda^2. */
+            double u1, u2, u3, u4;
+            draw2(seed, site, c1, sweep, 4u * a + 0u, &u1, &u2);
+            draw2(seed, site, c1, sweep, 4u * a + 1u, &u3, &u4);
+            double c = cos(2.0 * OR_PI * u2);
+            double lam2 = -(log(u1) + c * c * log(u3)) / (2.0 * alpha);
+            if (lam2 <= 1.0 && u4 * u4 <= 1.0 - lam2) {
+                x0 = 1.0 - 2.0 * lam2;
+                xlen = 2.0 * sqrt(lam2 * (1.0 - lam2));
+                accepted = 1;
+            }
+        } else {
+            /* Creutz: x0 from exp(alpha x0) on [-1,1] by inversion, accept
+             * with probability sqrt(1 - x0^2). */
+            double u1, u2;
+            draw2(seed, site, c1, sweep, 4u * a + 0u, &u1, &u2);
+            double t;
+            if (alpha < 1e-8) {
+                t = 2.0 * u1 - 1.0;
+            } else {
+                double e = exp(-2.0 * alpha);
+                t = 1.0 + log(e + u1 * (1.0 - e)) / alpha;
+            }
+            if (u2 * u2 <= 1.0 - t * t) {
+                x0 = t;
+                double s = 1.0 - t * t;
+                xlen = sqrt(s > 0.0 ? s : 0.0);
+                accepted = 1;
+            }
+        }
+    }
+    if (!accepted)
+        return OR_FLAG_CAP;
+
+    /* Direction of (w1,w2,w3): uniform on the unit 2-sphere. */
+    double u5, u6;
+    draw2(seed, site, c1, sweep, 2u, &u5, &u6);
+    double cth = 2.0 * u5 - 1.0;
+    double s = 1.0 - cth * cth;
+    double sth = sqrt(s > 0.0 ? s : 0.0);
+    double phi = 2.0 * OR_PI * u6;
+    double W[4] = {x0, xlen * sth * cos(phi), xlen * sth * sin(phi), xlen * cth};
+
+    double Vd[4];
+    or_qdag(Vhat, Vd);
+    or_qmul(W, Vd, Ulink);
+    return 0;
+}
+
+/* One checkerboard half-sweep: every link U_mu(x) with parity(x) = parity.
+ * Links of one (mu, parity) class never appear in each other's staples. */
+uint32_t or_heatbath_halfsweep(const int n[4], double *U, double beta, uint64_t seed,
+                               uint32_t sweep, int mu, int parity, uint32_t lattice_id)
+{
+    int64_t vol = or_volume(n);
+    uint32_t c1 = (uint32_t)(mu + 4 * 1 + 16 * lattice_id);
+    uint32_t flags = 0;
+#pragma omp parallel for schedule(static) reduction(| : flags)
+    for (int64_t i = 0; i < vol; ++i) {
+        if (or_parity(n, i) != parity)
+            continue;
+        double V[4];
+        or_staple(n, U, i, mu, V);
+        flags |= heatbath_link(U + (i * 4 + mu) * 4, V, beta, seed, (uint32_t)i, c1, sweep);
+    }
+    return flags;
+}
+
+/* A sweep: mu = x, y, z, t in turn, even sites before odd sites. */
+uint32_t or_heatbath_sweep(const int n[4], double *U, double beta, uint64_t seed,
+                           uint32_t sweep, uint32_t lattice_id)
+{
+    uint32_t flags = 0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int p = 0; p < 2; ++p)
+            flags |= or_heatbath_halfsweep(n, U, beta, seed, sweep, mu, p, lattice_id);
+    return flags;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Overrelaxation (Creutz 1987): U -> Vhat^dagger U^dagger Vhat^dagger keeps */
+/* Tr(U V) and is its own inverse; links with V = 0 are left alone.          */
+/* ------------------------------------------------------------------------ */
+uint32_t or_overrelax_halfsweep(const int n[4], double *U, int mu, int parity)
+{
+    int64_t vol = or_volume(n);
+    uint32_t flags = 0;
+#pragma omp parallel for schedule(static) reduction(| : flags)
+    for (int64_t i = 0; i < vol; ++i) {
+        if (or_parity(n, i) != parity)
+            continue;
+        double V[4];
+        or_staple(n, U, i, mu, V);
+        double k = sqrt(V[0] * V[0] + V[1] * V[1] + V[2] * V[2] + V[3] * V[3]);
+        if (!isfinite(k)) {
+            flags |= OR_FLAG_NONFINITE;
+            continue;
+        }
+        if (k == 0.0)
+            continue;
+        double Vd[4], Ud[4], t[4];
+        for (int j = 0; j < 4; ++j)
+            Vd[j] = V[j] / k;
+        Vd[1] = -Vd[1];
+        Vd[2] = -Vd[2];
+        Vd[3] = -Vd[3];
+        double *Ul = U + (i * 4 + mu) * 4;
+        or_qdag(Ul, Ud);
+        or_qmul(Vd, Ud, t);
+        or_qmul(t, Vd, Ul);
+    }
+    return flags;
+}
+
+uint32_t or_overrelax_sweep(const int n[4], double *U)
+{
+    uint32_t flags = 0;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int p = 0; p < 2; ++p)
+            flags |= or_overrelax_halfsweep(n, U, mu, p);
+    return flags;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mean plaquette (Sec. 2.1): the average over all 6V plaquettes of          */
+/* (1/2) Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+].  planes[] holds the  */
+/* six per-plane averages in the order (01,02,03,12,13,23).  Per-site values */
+/* are stored first and summed afterwards in extended precision, so the sum */
+/* does not depend on the thread count.                                      */
+/* ------------------------------------------------------------------------ */
+static double plaq_one(const int n[4], const double *U, int64_t i, int mu, int nu)
+{
+    double a[4], b[4], c[4], d[4];
+    int64_t xmu = or_neighbor(n, i, mu, +1);
+    int64_t xnu = or_neighbor(n, i, nu, +1);
+    or_qmul(link(U, i, mu), link(U, xmu, nu), a);
+    or_qdag(link(U, xnu, mu), c);
+    or_qmul(a, c, b);
+    or_qdag(link(U, i, nu), c);
+    or_qmul(b, c, d);
+    return d[0];
+}
+
+double or_plaquette(const int n[4], const double *U, double planes[6])
+{
+    int64_t vol = or_volume(n);
+    double *per = (double *)malloc(sizeof(double) * (size_t)vol * 6);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < vol; ++i) {
+        int p = 0;
+        for (int mu = 0; mu < 4; ++mu)
+            for (int nu = mu + 1; nu < 4; ++nu)
+                per[i * 6 + p++] = plaq_one(n, U, i, mu, nu);
+    }
+    long double tot[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = 0; i < vol; ++i)
+        for (int p = 0; p < 6; ++p)
+            tot[p] += per[i * 6 + p];
+    free(per);
+    long double all = 0;
+    for (int p = 0; p < 6; ++p) {
+        if (planes)
+            planes[p] = (double)(tot[p] / (long double)vol);
+        all += tot[p];
+    }
+    return (double)(all / (6.0L * (long double)vol));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Polyakov loop (Sec. 2.2, eq. (1)): at each spatial site the half trace of */
+/* the ordered product U_t(x,0) U_t(x,1) ... U_t(x,Nt-1).  L is indexed by   */
+/* the spatial site x + Nx*(y + Ny*z).                                       */
+/* ------------------------------------------------------------------------ */
+void or_polyakov_field(const int n[4], const double *U, double *L)
+{
+    int64_t vs = (int64_t)n[0] * n[1] * n[2];
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < vs; ++s) {
+        double P[4] = {1.0, 0.0, 0.0, 0.0}, T[4];
+        for (int t = 0; t < n[3]; ++t) {
+            or_qmul(P, link(U, s + vs * t, 3), T);
+            memcpy(P, T, sizeof P);
+        }
+        L[s] = P[0];
+    }
+}
+
+/* out[0] = spatial average of L, out[1] = spatial average of |L|. */
+void or_polyakov(const int n[4], const double *U, double out[2])
+{
+    int64_t vs = (int64_t)n[0] * n[1] * n[2];
+    double *L = (double *)malloc(sizeof(double) * (size_t)vs);
+    or_polyakov_field(n, U, L);
+    long double s = 0, sa = 0;
+    for (int64_t i = 0; i < vs; ++i) {
+        s += L[i];
+        sa += fabs(L[i]);
+    }
+    free(L);
+    out[0] = (double)(s / (long double)vs);
+    out[1] = (double)(sa / (long double)vs);
+}
+
+/* On-axis correlator (Sec. 2.2, eq. (3)): for SU(2), L is real and
+ * (1/4) Tr L(y) Tr L(x)^dagger = L(y) L(x) with L normalised by 1/2, so
+ *   C(r) = (1/(3 Vs)) sum_x sum_{i=x,y,z} L(x) L(x + r e_i),
+ * for r = 1 .. min(Nx,Ny,Nz)/2.  C[r-1] receives C(r); returns the number
+ * of r values written. */
+int or_polyakov_corr(const int n[4], const double *U, double *C)
+{
+    int64_t vs = (int64_t)n[0] * n[1] * n[2];
+    double *L = (double *)malloc(sizeof(double) * (size_t)vs);
+    or_polyakov_field(n, U, L);
+    int ns = n[0];
+    if (n[1] < ns)
+        ns = n[1];
+    if (n[2] < ns)
+        ns = n[2];
+    int rmax = ns / 2;
+    for (int r = 1; r <= rmax; ++r) {
+        long double acc = 0;
+        for (int64_t s = 0; s < vs; ++s) {
+            int x = (int)(s % n[0]);
+            int y = (int)((s / n[0]) % n[1]);
+            int z = (int)(s / ((int64_t)n[0] * n[1]));
+            int64_t sx = (x + r) % n[0] + (int64_t)n[0] * (y + (int64_t)n[1] * z);
+            int64_t sy = x + (int64_t)n[0] * ((y + r) % n[1] + (int64_t)n[1] * z);
+            int64_t sz = x + (int64_t)n[0] * (y + (int64_t)n[1] * ((z + r) % n[2]));
+            acc += (long double)L[s] * L[sx] + (long double)L[s] * L[sy] +
+                   (long double)L[s] * L[sz];
+        }
+        C[r - 1] = (double)(acc / (3.0L * (long double)vs));
+    }
+    free(L);
+    return rmax;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random gauge transformation, g(x) Haar-random (Philox kind 3).            */
+/* ------------------------------------------------------------------------ */
+void or_gauge_transform(const int n[4], double *U, uint64_t seed, uint32_t lattice_id)
+{
+    int64_t vol = or_volume(n);
+    double *g = (double *)malloc(sizeof(double) * (size_t)vol * 4);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < vol; ++i)
+        haar_from_counter(seed, (uint32_t)i, (uint32_t)(4 * 3 + 16 * lattice_id), 0u, g + 4 * i);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < vol; ++i) {
+        for (int mu = 0; mu < 4; ++mu) {
+            int64_t j = or_neighbor(n, i, mu, +1);
+            double t[4], gd[4];
+            double *Ul = U + (i * 4 + mu) * 4;
+            or_qmul(g + 4 * i, Ul, t);
+            or_qdag(g + 4 * j, gd);
+            or_qmul(t, gd, Ul);
+        }
+    }
+    free(g);
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
