@@ -1,0 +1,198 @@
+"""Benchmark: SU(2) link updates per second on one MI355X.
+
+One step = one pass of the whole path on a resident lattice: 1 heat-bath
+sweep (8 checkerboard launches) + 4 overrelaxation sweeps (32 launches) +
+mean plaquette + Polyakov loop and its on-axis correlator.  Default workload:
+64^4 periodic lattice, beta = 2.3, FP32 links, hot start (Philox seed 1234).
+The value counts 20 V link updates per step (4 V heat bath + 16 V
+overrelaxation); the per-kernel roofline uses the algorithmic bytes of each
+update (heat bath 8 links, overrelaxation 9 links of 16 B in FP32).
+
+Prints ONE JSON line (rank 0).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
+METRIC = "SU(2) link updates/sec + % HBM roofline; eff. indep. Polyakov samples/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--shape", type=str, default="64,64,64,64")
+    ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--beta", type=float, default=2.3)
+    ap.add_argument("--or-per-hb", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=1234)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-shape", type=str, default="48,48,48,48")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="bytes of a plain device copy to run before the timed region "
+                         "(reference for hardware byte counters)")
+    return ap.parse_args()
+
+
+def cpu_baseline(shape, beta, seed, n_or):
+    """The FP64 CPU oracle timed on a bounded sample of the same workload."""
+    import numpy as np  # noqa: F401
+    import oracle
+    n = tuple(int(v) for v in shape.split(","))
+    vol = n[0] * n[1] * n[2] * n[3]
+    U = oracle.init_hot(n, seed)
+    t0 = time.perf_counter()
+    oracle.heatbath_sweep(n, U, beta, seed, 0)
+    for _ in range(n_or):
+        oracle.overrelax_sweep(n, U)
+    oracle.plaquette(n, U)
+    oracle.polyakov_corr(n, U)
+    dt = time.perf_counter() - t0
+    updates = 4 * vol * (1 + n_or)
+    return {
+        "value": updates / dt,
+        "unit": "link updates/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{'x'.join(map(str, n))} FP64 oracle, hot start, one step "
+                  f"(1 HB + {n_or} OR sweeps + plaquette + Polyakov/correlator), {dt:.2f} s wall",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the lattice update is single-GPU in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1104_5432_amd as su2
+
+    n = tuple(int(v) for v in args.shape.split(","))
+    vol = n[0] * n[1] * n[2] * n[3]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    lat = su2.Lattice(n, args.prec, device=dev)
+    su2.su2_init_hot(lat, args.seed)
+    plaq = torch.empty((max(args.steps, 1), 7), dtype=torch.float64, device=dev)
+    poly = torch.empty((max(args.steps, 1), 2), dtype=torch.float64, device=dev)
+    corr = torch.empty((max(args.steps, 1), max(1, min(n[:3]) // 2)), dtype=torch.float64, device=dev)
+
+    if args.calibrate_copy:
+        a = torch.empty(args.calibrate_copy, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    def step(s, ev=None):
+        if ev:
+            ev[0].record(stream)
+        su2.su2_heatbath_sweep(lat, args.beta, args.seed, s)
+        if ev:
+            ev[1].record(stream)
+        su2.su2_overrelax(lat, args.or_per_hb)
+        if ev:
+            ev[2].record(stream)
+        k = s - args.warmup if s >= args.warmup else 0
+        su2.su2_plaquette(lat, plaq[k])
+        su2.su2_polyakov(lat, poly[k], corr[k])
+
+    for s in range(args.warmup):
+        step(s)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i, evs[i])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    hb_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    or_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+
+    flags = int(su2.su2_get_flags(lat).item())
+    last_plaq = float(plaq[args.steps - 1, 0].item())
+    last_poly = float(poly[args.steps - 1, 1].item())
+
+    link_b = 16 if args.prec == "f32" else 32
+    half = vol // 2
+    or_launch_ms = or_ms / (8 * args.or_per_hb) if args.or_per_hb else float("nan")
+    hb_launch_ms = hb_ms / 8
+    or_bytes = half * 9 * link_b          # algorithmic bytes per overrelaxation launch
+    hb_bytes = half * 8 * link_b          # algorithmic bytes per heat-bath launch
+    or_gbs = or_bytes / (or_launch_ms * 1e-3) / 1e9
+    hb_gbs = hb_bytes / (hb_launch_ms * 1e-3) / 1e9
+    updates = 4 * vol * (1 + args.or_per_hb)
+    value = updates * args.steps / (ms_total * 1e-3)
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "link updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": f"SU(2) pure gauge {'^'.join([str(n[0]), '4']) if len(set(n)) == 1 else 'x'.join(map(str, n))} "
+                        f"periodic, beta={args.beta}, hot start (Philox seed {args.seed}), "
+                        f"{args.prec.upper()} links, per step 1 heat-bath + {args.or_per_hb} overrelaxation "
+                        f"sweeps + FP64 plaquette + Polyakov loop/correlator",
+            "lattice": list(n),
+            "beta": args.beta,
+            "or_per_hb": args.or_per_hb,
+            "link_updates_per_step": updates,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "overrelax_kernel",
+            "achieved": or_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": or_gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_launch": or_bytes,
+            "avg_launch_ms": or_launch_ms,
+        },
+        "heatbath_roofline": {
+            "kernel": "heatbath_kernel",
+            "achieved": hb_gbs,
+            "frac": hb_gbs / HBM_PEAK_GBS,
+            "bytes_per_launch": hb_bytes,
+            "avg_launch_ms": hb_launch_ms,
+        },
+        "sweep_roofline_frac": ((hb_bytes * 8 + or_bytes * 8 * args.or_per_hb) / ((hb_ms + or_ms) * 1e-3) / 1e9)
+                               / HBM_PEAK_GBS,
+        "wall_s_timed": wall,
+        "check": {"plaquette_last": last_plaq, "polyakov_abs_last": last_poly, "flags": flags},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(args.cpu_shape, args.beta, args.seed, args.or_per_hb)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,152 @@
+/*
+ * su2.h -- C ABI of libsu2.so: SU(2) lattice gauge configurations on one
+ * AMD Instinct MI355X (gfx950) by checkerboard heat bath and
+ * overrelaxation, with the per-sweep mean plaquette and Polyakov-loop
+ * reductions.
+ *
+ * Method: Cardoso, Cardoso & Bicudo, "Finite temperature lattice QCD with
+ * GPUs", Excited QCD 2011 -- Sec. 2.1 (random SU(2) start, heat-bath
+ * iterations, mean plaquette at every iteration, single and double
+ * precision) and Sec. 2.2 (Polyakov loop, eq. (1); Polyakov-loop
+ * correlator, eq. (3)).  The paper leaves the sampler, representation and
+ * random numbers unstated; this library uses the Kennedy-Pendleton (1985)
+ * sampler for alpha = beta*|V| >= 2 and Creutz (1980) below, Creutz (1987)
+ * overrelaxation and Philox4x32-10 (Salmon et al., SC'11).
+ *
+ * Conventions
+ *  - Extents n[4] = (Nx, Ny, Nz, Nt); each must be even and >= 2 and the
+ *    volume V = Nx*Ny*Nz*Nt must be below 2^32.
+ *  - Site i = x + Nx*(y + Ny*(z + Nz*t)); parity (x+y+z+t) mod 2;
+ *    checkerboard index cb = i/2 (a bijection within each parity).
+ *  - A link U_mu(x) is the unit quaternion (a0,a1,a2,a3) of the SU(2)
+ *    matrix a0 + i(a1 s1 + a2 s2 + a3 s3); mu = 0,1,2,3 = x,y,z,t.
+ *  - Link layout in device memory (part of the ABI), plane q = 2*mu + parity:
+ *      SU2_F32: float4 (a0,a1,a2,a3) at element q*(V/2) + cb;
+ *      SU2_F64: double2 (a0,a1) at element (2q)*(V/2) + cb and
+ *               double2 (a2,a3) at element (2q+1)*(V/2) + cb.
+ *  - Random numbers: Philox4x32-10 with key (seed lo32, seed hi32) and
+ *    counter (site i, mu + 4*kind + 16*lattice_id, sweep, 4*attempt + draw);
+ *    kind 0 = hot start, 1 = heat bath.  A heat-bath sweep is therefore a
+ *    pure function of (links, beta, seed, sweep, lattice_id).
+ *  - Wilson action S = beta * sum_P (1 - (1/2) Tr U_P).
+ *
+ * Memory and streams
+ *  - links and work are DEVICE pointers owned by the caller, 16-byte
+ *    aligned, of at least su2_links_bytes() and su2_workspace_bytes()
+ *    bytes.  The library never allocates, frees or synchronises.
+ *  - stream is a hipStream_t (NULL = the null stream).  Every call only
+ *    enqueues work on that stream; results written to device pointers are
+ *    valid once that stream reaches them.
+ *  - Calls on distinct lattices (distinct links/work) may run concurrently;
+ *    calls on one lattice must be ordered by the caller (one stream).
+ *
+ * Errors
+ *  - Every entry point returns SU2_OK (0) or a negative code.  All argument
+ *    checks happen before any HIP call, so a rejected call has no effect.
+ *    SU2_EHIP reports a failed launch; su2_last_error() then holds the HIP
+ *    message (thread-local).
+ *  - Device-side anomalies set sticky bits in a flags word in the workspace:
+ *    SU2_FLAG_CAP (a sampler hit its attempt cap; the link was kept) and
+ *    SU2_FLAG_NONFINITE (a staple was not finite; the link was kept).  Both
+ *    starts clear it; su2_get_flags() copies it out.
+ */
+#ifndef SU2_H
+#define SU2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SU2_F64 = 0, SU2_F32 = 1 };
+
+enum {
+    SU2_OK = 0,
+    SU2_EINVAL = -1, /* null lattice/pointer, bad precision, beta < 0 or not finite, bad mu/parity/count */
+    SU2_EDIMS = -2,  /* an extent odd or < 2, or V >= 2^32 */
+    SU2_EALIGN = -3, /* links, work or an output pointer not suitably aligned */
+    SU2_EWORK = -4,  /* work_bytes < su2_workspace_bytes() */
+    SU2_EHIP = -5    /* a HIP launch failed */
+};
+
+#define SU2_FLAG_CAP 1u
+#define SU2_FLAG_NONFINITE 2u
+#define SU2_MAX_ATTEMPTS 4096
+
+typedef struct su2_lattice {
+    int32_t n[4];        /* (Nx, Ny, Nz, Nt) */
+    int32_t prec;        /* SU2_F64 or SU2_F32 */
+    int32_t lattice_id;  /* 0 .. 2^27-1; enters the random-number counter */
+    void *links;         /* device, >= su2_links_bytes(n, prec) */
+    void *work;          /* device, >= su2_workspace_bytes(n, prec) */
+    uint64_t work_bytes; /* size of work in bytes */
+} su2_lattice_t;
+
+/* Bytes of link storage: 4 V links of 16 (F32) or 32 (F64) bytes.
+ * Returns 0 if the extents or precision are invalid. */
+uint64_t su2_links_bytes(const int32_t n[4], int32_t prec);
+
+/* Bytes of workspace: flags word, reduction partials, Polyakov-loop field.
+ * Returns 0 if the extents or precision are invalid. */
+uint64_t su2_workspace_bytes(const int32_t n[4], int32_t prec);
+
+/* Cold start: every link = identity (Sec. 2.1 "initialization").  Clears
+ * the flags word. */
+int su2_init_cold(const su2_lattice_t *lat, void *stream);
+
+/* Hot start (Sec. 2.1 "random SU(2) matrix initialization"): every link
+ * Haar-random, from four Box-Muller normals normalised onto the unit
+ * 3-sphere, computed in FP64 (F32 lattices store the rounded value,
+ * renormalised in FP32).  Clears the flags word. */
+int su2_init_hot(const su2_lattice_t *lat, uint64_t seed, void *stream);
+
+/* One heat-bath sweep (Sec. 2.1 "heat bath method"): for mu = 0..3, for
+ * parity 0 then 1, every link U_mu(x) of that class is replaced by a draw
+ * from exp((beta/2) Tr(U V)) dU, V the sum of its six staples.  Eight
+ * ordered launches on stream.  sweep is the random-number sweep index. */
+int su2_heatbath_sweep(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t sweep,
+                       void *stream);
+
+/* One checkerboard class (mu, parity) of su2_heatbath_sweep. */
+int su2_heatbath_halfsweep(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t sweep,
+                           int32_t mu, int32_t parity, void *stream);
+
+/* n_sweeps overrelaxation sweeps (same class order as the heat bath):
+ * U -> Vhat^dagger U^dagger Vhat^dagger, Vhat = V/|V|; links with V = 0 are
+ * kept.  Preserves the action, uses no random numbers.  F32 lattices are
+ * renormalised on every write.  n_sweeps >= 0. */
+int su2_overrelax(const su2_lattice_t *lat, int32_t n_sweeps, void *stream);
+
+/* One checkerboard class (mu, parity) of su2_overrelax. */
+int su2_overrelax_halfsweep(const su2_lattice_t *lat, int32_t mu, int32_t parity, void *stream);
+
+/* Mean plaquette (Sec. 2.1 "mean average plaquette"): d_out (device,
+ * 8-byte aligned, 7 doubles) receives [0] the average of (1/2) Tr U_P over
+ * all 6V plaquettes and [1..6] the per-plane averages for the planes
+ * (01, 02, 03, 12, 13, 23).  Half traces and all sums in FP64; the
+ * reduction order is fixed, so the result is bitwise reproducible. */
+int su2_plaquette(const su2_lattice_t *lat, double *d_out, void *stream);
+
+/* Polyakov loop (Sec. 2.2, eq. (1)) L(x) = (1/2) Tr prod_{t=0}^{Nt-1}
+ * U_t(x,t) at every spatial site.  d_out (device, 2 doubles) receives
+ * [0] the spatial mean of L and [1] the spatial mean of |L|.  If d_corr is
+ * not NULL it receives (device, R = min(Nx,Ny,Nz)/2 doubles) the on-axis
+ * correlator of eq. (3), C(r) = (1/(3 Vs)) sum_x sum_i L(x) L(x + r e_i),
+ * r = 1..R.  FP64 sums, fixed reduction order. */
+int su2_polyakov(const su2_lattice_t *lat, double *d_out, double *d_corr, void *stream);
+
+/* Copy the sticky flags word to d_flags (device, one uint32). */
+int su2_get_flags(const su2_lattice_t *lat, uint32_t *d_flags, void *stream);
+
+/* Message for an error code (static string). */
+const char *su2_strerror(int code);
+
+/* Detail of the last error on the calling thread (static per thread). */
+const char *su2_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,235 @@
+"""SU(2) lattice gauge configurations on an MI355X: Python binding of libsu2.so.
+
+The functions below carry the names of the C ABI in include/su2.h and only
+marshal arguments: every step of the heat bath, overrelaxation and the
+observables runs in the library's HIP kernels.  PyTorch provides device
+memory (uint8 tensors) and the current HIP stream.  Importing this package
+raises ImportError when libsu2.so has not been built; there is no fallback.
+
+Method: Cardoso, Cardoso & Bicudo, "Finite temperature lattice QCD with
+GPUs" (Excited QCD 2011), Sec. 2.1 (random start, heat-bath sweeps, mean
+plaquette per sweep) and Sec. 2.2, eqs. (1) and (3) (Polyakov loop and its
+correlator).
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsu2.so")
+
+SU2_F64, SU2_F32 = 0, 1
+SU2_OK, SU2_EINVAL, SU2_EDIMS, SU2_EALIGN, SU2_EWORK, SU2_EHIP = 0, -1, -2, -3, -4, -5
+SU2_FLAG_CAP, SU2_FLAG_NONFINITE = 1, 2
+SU2_MAX_ATTEMPTS = 4096
+
+_PRECS = {"f64": SU2_F64, "f32": SU2_F32, SU2_F64: SU2_F64, SU2_F32: SU2_F32}
+
+
+class su2_lattice_t(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 4),
+        ("prec", ctypes.c_int32),
+        ("lattice_id", ctypes.c_int32),
+        ("links", ctypes.c_void_p),
+        ("work", ctypes.c_void_p),
+        ("work_bytes", ctypes.c_uint64),
+    ]
+
+
+class Su2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_LP = ctypes.POINTER(su2_lattice_t)
+_I4 = ctypes.POINTER(ctypes.c_int32)
+_VP = ctypes.c_void_p
+_SIGNATURES = {
+    "su2_links_bytes": (ctypes.c_uint64, [_I4, ctypes.c_int32]),
+    "su2_workspace_bytes": (ctypes.c_uint64, [_I4, ctypes.c_int32]),
+    "su2_init_cold": (ctypes.c_int, [_LP, _VP]),
+    "su2_init_hot": (ctypes.c_int, [_LP, ctypes.c_uint64, _VP]),
+    "su2_heatbath_sweep": (ctypes.c_int, [_LP, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, _VP]),
+    "su2_heatbath_halfsweep": (ctypes.c_int, [_LP, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                              ctypes.c_int32, ctypes.c_int32, _VP]),
+    "su2_overrelax": (ctypes.c_int, [_LP, ctypes.c_int32, _VP]),
+    "su2_overrelax_halfsweep": (ctypes.c_int, [_LP, ctypes.c_int32, ctypes.c_int32, _VP]),
+    "su2_plaquette": (ctypes.c_int, [_LP, _VP, _VP]),
+    "su2_polyakov": (ctypes.c_int, [_LP, _VP, _VP, _VP]),
+    "su2_get_flags": (ctypes.c_int, [_LP, _VP, _VP]),
+    "su2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "su2_last_error": (ctypes.c_char_p, []),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+            "(hipcc for gfx950). There is no CPU fallback.")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != SU2_OK:
+        raise Su2Error(rc, f"{lib.su2_strerror(rc).decode()}: {lib.su2_last_error().decode()}")
+
+
+def _dims(n):
+    n = tuple(int(v) for v in n)
+    if len(n) != 4:
+        raise ValueError("extents must be (Nx, Ny, Nz, Nt)")
+    return n, (ctypes.c_int32 * 4)(*n)
+
+
+def su2_links_bytes(n, prec):
+    return int(lib.su2_links_bytes(_dims(n)[1], _PRECS[prec]))
+
+
+def su2_workspace_bytes(n, prec):
+    return int(lib.su2_workspace_bytes(_dims(n)[1], _PRECS[prec]))
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Lattice:
+    """Device storage for one lattice: links and workspace as uint8 tensors,
+    plus the su2_lattice_t descriptor that points at them."""
+
+    def __init__(self, n, prec="f64", device="cuda", lattice_id=0):
+        self.n, cn = _dims(n)
+        self.prec = _PRECS[prec]
+        nb = su2_links_bytes(self.n, self.prec)
+        wb = su2_workspace_bytes(self.n, self.prec)
+        if nb == 0 or wb == 0:
+            raise Su2Error(SU2_EDIMS, "extents must be even, >= 2, with volume < 2^32")
+        self.device = torch.device(device)
+        self.links = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.work = torch.zeros(wb, dtype=torch.uint8, device=self.device)
+        self.desc = su2_lattice_t(cn, self.prec, int(lattice_id), self.links.data_ptr(),
+                                  self.work.data_ptr(), wb)
+
+    @property
+    def volume(self):
+        nx, ny, nz, nt = self.n
+        return nx * ny * nz * nt
+
+    @property
+    def dtype(self):
+        return torch.float32 if self.prec == SU2_F32 else torch.float64
+
+    def ref(self):
+        return ctypes.byref(self.desc)
+
+
+def su2_init_cold(lat, stream=None):
+    _check(lib.su2_init_cold(lat.ref(), _stream(stream)))
+
+
+def su2_init_hot(lat, seed, stream=None):
+    _check(lib.su2_init_hot(lat.ref(), int(seed), _stream(stream)))
+
+
+def su2_heatbath_sweep(lat, beta, seed, sweep, stream=None):
+    _check(lib.su2_heatbath_sweep(lat.ref(), float(beta), int(seed), int(sweep), _stream(stream)))
+
+
+def su2_heatbath_halfsweep(lat, beta, seed, sweep, mu, parity, stream=None):
+    _check(lib.su2_heatbath_halfsweep(lat.ref(), float(beta), int(seed), int(sweep), int(mu), int(parity),
+                                      _stream(stream)))
+
+
+def su2_overrelax(lat, n_sweeps=1, stream=None):
+    _check(lib.su2_overrelax(lat.ref(), int(n_sweeps), _stream(stream)))
+
+
+def su2_overrelax_halfsweep(lat, mu, parity, stream=None):
+    _check(lib.su2_overrelax_halfsweep(lat.ref(), int(mu), int(parity), _stream(stream)))
+
+
+def su2_plaquette(lat, out=None, stream=None):
+    """Enqueue the mean plaquette; returns the device tensor (7 float64):
+    [mean, planes 01, 02, 03, 12, 13, 23]."""
+    if out is None:
+        out = torch.empty(7, dtype=torch.float64, device=lat.device)
+    _check(lib.su2_plaquette(lat.ref(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def su2_polyakov(lat, out=None, corr=None, with_corr=True, stream=None):
+    """Enqueue the Polyakov loop; returns (out, corr) device tensors:
+    out = [mean L, mean |L|], corr = C(r) for r = 1 .. min(Nx,Ny,Nz)/2 (or None)."""
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=lat.device)
+    if corr is None and with_corr:
+        corr = torch.empty(max(1, min(lat.n[:3]) // 2), dtype=torch.float64, device=lat.device)
+    _check(lib.su2_polyakov(lat.ref(), out.data_ptr(), corr.data_ptr() if corr is not None else None,
+                            _stream(stream)))
+    return out, corr
+
+
+def su2_get_flags(lat, out=None, stream=None):
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device=lat.device)
+    _check(lib.su2_get_flags(lat.ref(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Layout conversion between the library's checkerboard planes and the
+# canonical site-major layout U[t][z][y][x][mu][4] (float64, host).  The link
+# layout is part of the ABI (include/su2.h); these helpers only re-index.
+# ---------------------------------------------------------------------------
+def _site_tables(n, device):
+    nx, ny, nz, nt = n
+    t, z, y, x = torch.meshgrid(*[torch.arange(v, device=device) for v in (nt, nz, ny, nx)], indexing="ij")
+    par = ((x + y + z + t) % 2).reshape(-1)
+    cb = ((x + nx * (y + ny * (z + nz * t))) // 2).reshape(-1)
+    return par, cb
+
+
+def _planes(lat):
+    half = lat.volume // 2
+    if lat.prec == SU2_F32:
+        return lat.links.view(torch.float32).view(4, 2, half, 4)
+    return lat.links.view(torch.float64).view(4, 2, 2, half, 2)
+
+
+def to_canonical(lat):
+    """Copy the links out as a float64 CPU tensor of shape (Nt,Nz,Ny,Nx,4,4)."""
+    par, cb = _site_tables(lat.n, lat.device)
+    P = _planes(lat)
+    if lat.prec == SU2_F32:
+        q = P[:, par, cb, :].permute(1, 0, 2)               # (V, mu, 4)
+    else:
+        q = P[:, par, :, cb, :].reshape(-1, 4, 4)           # (V, mu, sub, 2) -> (V, mu, 4)
+    nx, ny, nz, nt = lat.n
+    return q.to(torch.float64).cpu().reshape(nt, nz, ny, nx, 4, 4).contiguous()
+
+
+def from_canonical(lat, U):
+    """Overwrite the links from a canonical (Nt,Nz,Ny,Nx,4,4) array (rounded to F32 if needed)."""
+    U = torch.as_tensor(U, dtype=torch.float64).reshape(-1, 4, 4).to(lat.device)
+    par, cb = _site_tables(lat.n, lat.device)
+    P = _planes(lat)
+    if lat.prec == SU2_F32:
+        P[:, par, cb, :] = U.permute(1, 0, 2).to(torch.float32)
+    else:
+        P[:, par, :, cb, :] = U.reshape(-1, 4, 2, 2)

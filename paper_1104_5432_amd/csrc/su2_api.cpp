@@ -1,0 +1,296 @@
+// su2_api.cpp -- the C ABI declared in include/su2.h: argument checks (all
+// before any HIP call), workspace layout, launch sequencing, error codes.
+#include "su2.h"
+#include "su2_launch.hpp"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int fail(int code, const char *msg)
+{
+    std::snprintf(g_last_error, sizeof g_last_error, "%s", msg);
+    return code;
+}
+
+bool dims_ok(const int32_t n[4])
+{
+    if (!n)
+        return false;
+    uint64_t vol = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (n[d] < 2 || (n[d] & 1))
+            return false;
+        vol *= (uint64_t)n[d];
+        if (vol >= (1ull << 32))
+            return false;
+    }
+    return true;
+}
+
+bool prec_ok(int32_t p)
+{
+    return p == SU2_F64 || p == SU2_F32;
+}
+
+bool aligned(const void *p, uintptr_t a)
+{
+    return ((uintptr_t)p % a) == 0;
+}
+
+// Common checks of a lattice descriptor.
+int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayout *wl)
+{
+    if (!lat)
+        return fail(SU2_EINVAL, "lattice descriptor is NULL");
+    if (!prec_ok(lat->prec))
+        return fail(SU2_EINVAL, "precision must be SU2_F64 or SU2_F32");
+    if (!dims_ok(lat->n))
+        return fail(SU2_EDIMS, "extents must be even, >= 2, with volume < 2^32");
+    if (lat->lattice_id < 0 || lat->lattice_id >= (1 << 27))
+        return fail(SU2_EINVAL, "lattice_id must be in [0, 2^27)");
+    if (!lat->links || !lat->work)
+        return fail(SU2_EINVAL, "links and work must be non-NULL device pointers");
+    if (!aligned(lat->links, 16) || !aligned(lat->work, 16))
+        return fail(SU2_EALIGN, "links and work must be 16-byte aligned");
+    const su2::WorkLayout w = su2::work_layout(lat->n);
+    if (lat->work_bytes < w.total)
+        return fail(SU2_EWORK, "work_bytes is smaller than su2_workspace_bytes()");
+    out->n[0] = lat->n[0];
+    out->n[1] = lat->n[1];
+    out->n[2] = lat->n[2];
+    out->n[3] = lat->n[3];
+    out->prec = lat->prec;
+    out->lattice_id = lat->lattice_id;
+    out->volume = (uint64_t)lat->n[0] * lat->n[1] * lat->n[2] * lat->n[3];
+    out->links = lat->links;
+    out->work = static_cast<char *>(lat->work);
+    out->flags = reinterpret_cast<uint32_t *>(lat->work);
+    if (wl)
+        *wl = w;
+    return SU2_OK;
+}
+
+int check_class(int32_t mu, int32_t parity)
+{
+    if (mu < 0 || mu > 3 || (parity != 0 && parity != 1))
+        return fail(SU2_EINVAL, "mu must be 0..3 and parity 0 or 1");
+    return SU2_OK;
+}
+
+int check_beta(double beta)
+{
+    if (!std::isfinite(beta) || beta < 0.0)
+        return fail(SU2_EINVAL, "beta must be finite and >= 0");
+    return SU2_OK;
+}
+
+int launched()
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        std::snprintf(g_last_error, sizeof g_last_error, "HIP: %s", hipGetErrorString(e));
+        return SU2_EHIP;
+    }
+    return SU2_OK;
+}
+
+uint64_t round256(uint64_t b)
+{
+    return (b + 255) & ~uint64_t(255);
+}
+
+} // namespace
+
+namespace su2 {
+
+WorkLayout work_layout(const int32_t n[4])
+{
+    const uint64_t vol = (uint64_t)n[0] * n[1] * n[2] * n[3];
+    const uint64_t vs = (uint64_t)n[0] * n[1] * n[2];
+    int ns = n[0] < n[1] ? n[0] : n[1];
+    ns = ns < n[2] ? ns : n[2];
+    WorkLayout w;
+    w.rmax = ns / 2;
+    auto blocks = [](uint64_t items, uint64_t cap) {
+        uint64_t b = (items + 255) / 256;
+        return (uint32_t)(b < cap ? (b > 0 ? b : 1) : cap);
+    };
+    w.nblk_plaq = blocks(vol, 4096);
+    w.nblk_poly = blocks(vs, 2048);
+    w.nblk_corr = blocks(vs, 1024);
+    uint64_t off = 256; // flags word
+    w.off_plaq = off;
+    off += round256((uint64_t)w.nblk_plaq * 6 * sizeof(double));
+    w.off_poly = off;
+    off += round256((uint64_t)w.nblk_poly * 2 * sizeof(double));
+    w.off_corr = off;
+    off += round256((uint64_t)w.nblk_corr * (uint64_t)(w.rmax > 0 ? w.rmax : 1) * sizeof(double));
+    w.off_lfield = off;
+    off += round256(vs * sizeof(double));
+    w.total = off;
+    return w;
+}
+
+} // namespace su2
+
+extern "C" {
+
+uint64_t su2_links_bytes(const int32_t n[4], int32_t prec)
+{
+    if (!dims_ok(n) || !prec_ok(prec))
+        return 0;
+    const uint64_t vol = (uint64_t)n[0] * n[1] * n[2] * n[3];
+    return vol * 4u * (prec == SU2_F32 ? 16u : 32u);
+}
+
+uint64_t su2_workspace_bytes(const int32_t n[4], int32_t prec)
+{
+    if (!dims_ok(n) || !prec_ok(prec))
+        return 0;
+    return su2::work_layout(n).total;
+}
+
+int su2_init_cold(const su2_lattice_t *lat, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lattice(lat, &a, nullptr);
+    if (rc)
+        return rc;
+    su2::launch_init(a, 0, 0, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_init_hot(const su2_lattice_t *lat, uint64_t seed, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lattice(lat, &a, nullptr);
+    if (rc)
+        return rc;
+    su2::launch_init(a, 1, seed, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_heatbath_halfsweep(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t sweep, int32_t mu,
+                           int32_t parity, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lattice(lat, &a, nullptr);
+    if (!rc)
+        rc = check_beta(beta);
+    if (!rc)
+        rc = check_class(mu, parity);
+    if (rc)
+        return rc;
+    su2::launch_heatbath(a, beta, seed, sweep, mu, parity, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_heatbath_sweep(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t sweep, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lattice(lat, &a, nullptr);
+    if (!rc)
+        rc = check_beta(beta);
+    if (rc)
+        return rc;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int p = 0; p < 2; ++p)
+            su2::launch_heatbath(a, beta, seed, sweep, mu, p, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_overrelax_halfsweep(const su2_lattice_t *lat, int32_t mu, int32_t parity, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lattice(lat, &a, nullptr);
+    if (!rc)
+        rc = check_class(mu, parity);
+    if (rc)
+        return rc;
+    su2::launch_overrelax(a, mu, parity, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_overrelax(const su2_lattice_t *lat, int32_t n_sweeps, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lattice(lat, &a, nullptr);
+    if (rc)
+        return rc;
+    if (n_sweeps < 0)
+        return fail(SU2_EINVAL, "n_sweeps must be >= 0");
+    for (int s = 0; s < n_sweeps; ++s)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int p = 0; p < 2; ++p)
+                su2::launch_overrelax(a, mu, p, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_plaquette(const su2_lattice_t *lat, double *d_out, void *stream)
+{
+    su2::LaunchArgs a;
+    su2::WorkLayout w;
+    int rc = check_lattice(lat, &a, &w);
+    if (rc)
+        return rc;
+    if (!d_out)
+        return fail(SU2_EINVAL, "d_out must be a device pointer to 7 doubles");
+    if (!aligned(d_out, 8))
+        return fail(SU2_EALIGN, "d_out must be 8-byte aligned");
+    su2::launch_plaquette(a, w, d_out, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_polyakov(const su2_lattice_t *lat, double *d_out, double *d_corr, void *stream)
+{
+    su2::LaunchArgs a;
+    su2::WorkLayout w;
+    int rc = check_lattice(lat, &a, &w);
+    if (rc)
+        return rc;
+    if (!d_out)
+        return fail(SU2_EINVAL, "d_out must be a device pointer to 2 doubles");
+    if (!aligned(d_out, 8) || (d_corr && !aligned(d_corr, 8)))
+        return fail(SU2_EALIGN, "d_out and d_corr must be 8-byte aligned");
+    su2::launch_polyakov(a, w, d_out, d_corr, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_get_flags(const su2_lattice_t *lat, uint32_t *d_flags, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lattice(lat, &a, nullptr);
+    if (rc)
+        return rc;
+    if (!d_flags)
+        return fail(SU2_EINVAL, "d_flags must be a device pointer");
+    if (!aligned(d_flags, 4))
+        return fail(SU2_EALIGN, "d_flags must be 4-byte aligned");
+    su2::launch_get_flags(a, d_flags, (hipStream_t)stream);
+    return launched();
+}
+
+const char *su2_strerror(int code)
+{
+    switch (code) {
+    case SU2_OK: return "ok";
+    case SU2_EINVAL: return "invalid argument";
+    case SU2_EDIMS: return "invalid lattice extents";
+    case SU2_EALIGN: return "misaligned pointer";
+    case SU2_EWORK: return "workspace too small";
+    case SU2_EHIP: return "HIP launch failed";
+    default: return "unknown error";
+    }
+}
+
+const char *su2_last_error(void)
+{
+    return g_last_error;
+}
+
+} // extern "C"

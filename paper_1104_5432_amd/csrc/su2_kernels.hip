@@ -1,0 +1,477 @@
+// su2_kernels.hip -- gfx950 kernels of the SU(2) heat-bath library and their
+// launchers.  One thread per link of a checkerboard class (mu, parity): the
+// links of one class never appear in each other's staples, so a class is
+// updated in one launch without synchronisation.  All reductions are
+// deterministic: wave64 shuffles, an LDS tree, one partial per block and a
+// fixed-order final pass.
+#include "su2_device.hpp"
+#include "su2_launch.hpp"
+
+namespace su2 {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Staple sum of U_mu(x) (x of parity `par`, checkerboard index cb):
+//   V = sum_{nu != mu} U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+//                    + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
+// so that the link's local action is -(beta/2) Tr(U_mu(x) V).
+// ---------------------------------------------------------------------------
+template <class T, int MU>
+__device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, const Site &s, uint32_t cb,
+                                          int par)
+{
+    const int opp = par ^ 1;
+    const uint32_t cb_xp = cb_shift(g, s.c, MU == 0, MU == 1, MU == 2, MU == 3);
+    Quat<T> V = {0, 0, 0, 0};
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU)
+            continue;
+        const int32_t e0 = (nu == 0), e1 = (nu == 1), e2 = (nu == 2), e3 = (nu == 3);
+        const int32_t m0 = (MU == 0), m1 = (MU == 1), m2 = (MU == 2), m3 = (MU == 3);
+        const uint32_t cb_xpn = cb_shift(g, s.c, e0, e1, e2, e3);
+        const uint32_t cb_xmn = cb_shift(g, s.c, -e0, -e1, -e2, -e3);
+        const uint32_t cb_xpmn = cb_shift(g, s.c, m0 - e0, m1 - e1, m2 - e2, m3 - e3);
+        // upper staple
+        const Quat<T> a = U.ld(nu, opp, cb_xp);
+        const Quat<T> b = U.ld(MU, opp, cb_xpn);
+        const Quat<T> c = U.ld(nu, par, cb);
+        qacc(V, qmul_nd(qmul_nd(a, b), c));
+        // lower staple
+        const Quat<T> d = U.ld(nu, par, cb_xpmn);
+        const Quat<T> e = U.ld(MU, opp, cb_xmn);
+        const Quat<T> f = U.ld(nu, opp, cb_xmn);
+        qacc(V, qmul(qmul_dd(d, e), f));
+    }
+    return V;
+}
+
+// ---------------------------------------------------------------------------
+// Heat bath for one class.  With k = |V|, Vhat = V/k and alpha = beta k, the
+// new link is W Vhat^dagger where W has density ~ exp(alpha w0) w.r.t. Haar
+// measure: w0 by Kennedy-Pendleton (alpha >= 2) or Creutz (alpha < 2), the
+// vector part isotropic with length sqrt(1 - w0^2).  Random numbers: counter
+// (site, c1, sweep, 4*attempt + draw); draws 0,1 feed the sampler attempt,
+// draw 2 (of attempt 0) the direction.  The sampler runs in FP64 for both
+// link precisions.
+// ---------------------------------------------------------------------------
+template <class T, int MU>
+__global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, int par, double beta,
+                                                           uint32_t k0, uint32_t k1, uint32_t c1,
+                                                           uint32_t sweep, uint32_t *flags)
+{
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t cb = tile * kBlock + threadIdx.x;
+    if (cb >= g.half)
+        return;
+    const Site s = site_of_cb(g, cb, par);
+    const Quat<T> V = staple<T, MU>(U, g, s, cb, par);
+    const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
+    const T k = sqrt(k2);
+    if (!isfinite(k)) {
+        atomicOr(flags, kFlagNonFinite);
+        return;
+    }
+    Quat<T> Vh = {1, 0, 0, 0};
+    if (k > T(0)) {
+        const T inv = T(1) / k;
+        Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
+    }
+    const double alpha = beta * (double)k;
+
+    double x0 = 0.0, xlen = 0.0;
+    bool ok = false;
+    if (alpha >= 2.0) {
+        const double inv2a = 1.0 / (2.0 * alpha);
+        for (uint32_t a = 0; a < kMaxAttempts; ++a) {
+            double u1, u2, u3, u4;
+            Draw<T>::two(philox(s.site, c1, sweep, 4u * a, k0, k1), u1, u2);
+            Draw<T>::two(philox(s.site, c1, sweep, 4u * a + 1u, k0, k1), u3, u4);
+            const double c = cos((2.0 * kPi) * u2);
+            const double lam2 = -(log(u1) + c * c * log(u3)) * inv2a;
+            if (lam2 <= 1.0 && u4 * u4 <= 1.0 - lam2) {
+                x0 = 1.0 - 2.0 * lam2;
+                xlen = 2.0 * sqrt(lam2 * (1.0 - lam2));
+                ok = true;
+                break;
+            }
+        }
+    } else {
+        const double e = exp(-2.0 * alpha);
+        for (uint32_t a = 0; a < kMaxAttempts; ++a) {
+            double u1, u2;
+            Draw<T>::two(philox(s.site, c1, sweep, 4u * a, k0, k1), u1, u2);
+            const double t = (alpha < 1e-8) ? 2.0 * u1 - 1.0 : 1.0 + log(e + u1 * (1.0 - e)) / alpha;
+            if (u2 * u2 <= 1.0 - t * t) {
+                x0 = t;
+                xlen = sqrt(fmax(0.0, 1.0 - t * t));
+                ok = true;
+                break;
+            }
+        }
+    }
+    if (!ok) {
+        atomicOr(flags, kFlagCap);
+        return;
+    }
+    double u5, u6;
+    Draw<T>::two(philox(s.site, c1, sweep, 2u, k0, k1), u5, u6);
+    const double cth = 2.0 * u5 - 1.0;
+    const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+    double sph, cph;
+    sincos((2.0 * kPi) * u6, &sph, &cph);
+    const Quat<T> X = {(T)x0, (T)(xlen * sth * cph), (T)(xlen * sth * sph), (T)(xlen * cth)};
+    U.st(MU, par, cb, unitize(qmul_nd(X, Vh)));
+}
+
+// ---------------------------------------------------------------------------
+// Overrelaxation for one class: U -> Vhat^+ U^+ Vhat^+ = (Vhat U Vhat)^+.
+// ---------------------------------------------------------------------------
+template <class T, int MU>
+__global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags)
+{
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t cb = tile * kBlock + threadIdx.x;
+    if (cb >= g.half)
+        return;
+    const Site s = site_of_cb(g, cb, par);
+    const Quat<T> V = staple<T, MU>(U, g, s, cb, par);
+    const Quat<T> u = U.ld(MU, par, cb);
+    const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
+    const T k = sqrt(k2);
+    if (!isfinite(k)) {
+        atomicOr(flags, kFlagNonFinite);
+        return;
+    }
+    if (k == T(0))
+        return;
+    const T inv = T(1) / k;
+    const Quat<T> Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
+    const Quat<T> w = qmul(qmul(Vh, u), Vh);
+    U.st(MU, par, cb, unitize(Quat<T>{w.w, -w.x, -w.y, -w.z}));
+}
+
+// ---------------------------------------------------------------------------
+// Starts.  Hot: four Box-Muller normals from two Philox calls (counter
+// (site, mu + 16*lattice_id, 0, 0/1)), normalised; always computed in FP64.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(kBlock) void init_kernel(Links<T> U, Geom g, int hot, uint32_t k0, uint32_t k1,
+                                                       uint32_t lid16, uint32_t *flags)
+{
+    const uint32_t cb = blockIdx.x * kBlock + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *flags = 0u;
+    if (cb >= g.half)
+        return;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        const Site s = site_of_cb(g, cb, par);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            Quat<double> q = {1.0, 0.0, 0.0, 0.0};
+            if (hot) {
+                const uint32_t c1 = (uint32_t)mu + lid16;
+                double u1, u2, u3, u4;
+                Draw<double>::two(philox(s.site, c1, 0u, 0u, k0, k1), u1, u2);
+                Draw<double>::two(philox(s.site, c1, 0u, 1u, k0, k1), u3, u4);
+                const double ra = sqrt(-2.0 * log(u1));
+                const double rb = sqrt(-2.0 * log(u3));
+                double sa, ca, sb, cbv;
+                sincos((2.0 * kPi) * u2, &sa, &ca);
+                sincos((2.0 * kPi) * u4, &sb, &cbv);
+                const double g0 = ra * ca, g1 = ra * sa, g2 = rb * cbv, g3 = rb * sb;
+                const double nrm = sqrt(g0 * g0 + g1 * g1 + g2 * g2 + g3 * g3);
+                q = {g0 / nrm, g1 / nrm, g2 / nrm, g3 / nrm};
+            }
+            U.st(mu, par, cb, unitize(Quat<T>{(T)q.w, (T)q.x, (T)q.y, (T)q.z}));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the block; thread 0 returns the totals.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[NV])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = wave_sum(v[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            lds[wave][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w)
+                s += lds[w][j];
+            v[j] = s;
+        }
+    }
+}
+
+// Plaquettes: every site x (both parities) sums (1/2) Tr of its six
+// plaquettes U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+, mu < nu, in FP64.
+template <class T>
+__global__ __launch_bounds__(kBlock) void plaquette_kernel(Links<T> U, Geom g, double *partials)
+{
+    __shared__ double lds[kBlock / 64][6];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const uint32_t total = 2u * g.half;
+    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
+        const int par = idx >= g.half;
+        const uint32_t cb = idx - (par ? g.half : 0u);
+        const int opp = par ^ 1;
+        const Site s = site_of_cb(g, cb, par);
+        Quat<T> own[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+            own[mu] = U.ld(mu, par, cb);
+        uint32_t cbp[4];
+        cbp[0] = cb_shift(g, s.c, 1, 0, 0, 0);
+        cbp[1] = cb_shift(g, s.c, 0, 1, 0, 0);
+        cbp[2] = cb_shift(g, s.c, 0, 0, 1, 0);
+        cbp[3] = cb_shift(g, s.c, 0, 0, 0, 1);
+        int p = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                const Quat<T> a = qmul(own[mu], U.ld(nu, opp, cbp[mu]));
+                const Quat<T> b = qmul(own[nu], U.ld(mu, opp, cbp[nu]));
+                acc[p++] += (double)qdot(a, b);
+            }
+    }
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            partials[(size_t)blockIdx.x * 6 + j] = acc[j];
+}
+
+// Polyakov loop at each spatial site: ordered product of the Nt temporal links.
+template <class T>
+__global__ __launch_bounds__(kBlock) void polyakov_kernel(Links<T> U, Geom g, double *Lfield, double *partials)
+{
+    __shared__ double lds[kBlock / 64][2];
+    double acc[2] = {0, 0};
+    for (uint32_t sp = blockIdx.x * kBlock + threadIdx.x; sp < g.vs; sp += gridDim.x * kBlock) {
+        const uint32_t yz = fdiv(sp, g.div_nx);
+        const uint32_t x = sp - yz * (uint32_t)g.n[0];
+        const uint32_t z = fdiv(yz, g.div_ny);
+        const uint32_t y = yz - z * (uint32_t)g.n[1];
+        Quat<T> P = {1, 0, 0, 0};
+        for (int t = 0; t < g.n[3]; ++t) {
+            const uint32_t site = sp + g.vs * (uint32_t)t;
+            const int par = (int)((x + y + z + (uint32_t)t) & 1u);
+            P = qmul(P, U.ld(3, par, site >> 1));
+        }
+        const double L = (double)P.w;
+        Lfield[sp] = L;
+        acc[0] += L;
+        acc[1] += fabs(L);
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        partials[(size_t)blockIdx.x * 2 + 0] = acc[0];
+        partials[(size_t)blockIdx.x * 2 + 1] = acc[1];
+    }
+}
+
+// On-axis Polyakov correlator: for r = 1..R, sum_x L(x)(L(x+r e_x) + L(x+r e_y) + L(x+r e_z)).
+__global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, Geom g, int R, double *partials)
+{
+    __shared__ double lds[kBlock / 64][1];
+    const uint32_t nx = (uint32_t)g.n[0], ny = (uint32_t)g.n[1], nz = (uint32_t)g.n[2];
+    for (int r = 1; r <= R; ++r) {
+        double acc[1] = {0.0};
+        for (uint32_t sp = blockIdx.x * kBlock + threadIdx.x; sp < g.vs; sp += gridDim.x * kBlock) {
+            const uint32_t yz = fdiv(sp, g.div_nx);
+            const uint32_t x = sp - yz * nx;
+            const uint32_t z = fdiv(yz, g.div_ny);
+            const uint32_t y = yz - z * ny;
+            const uint32_t xr = x + (uint32_t)r, yr = y + (uint32_t)r, zr = z + (uint32_t)r;
+            const uint32_t xs = xr >= nx ? xr - nx : xr;
+            const uint32_t ys = yr >= ny ? yr - ny : yr;
+            const uint32_t zs = zr >= nz ? zr - nz : zr;
+            const double L = Lfield[sp];
+            acc[0] += L * (Lfield[xs + nx * (y + ny * z)] + Lfield[x + nx * (ys + ny * z)] +
+                           Lfield[x + nx * (y + ny * zs)]);
+        }
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0)
+            partials[(size_t)blockIdx.x * R + (r - 1)] = acc[0];
+        __syncthreads();
+    }
+}
+
+// out[c] = scale * sum_b partials[b*ncol + c], one block per column, fixed order.
+__global__ __launch_bounds__(kBlock) void colsum_kernel(const double *partials, uint32_t nblk, int ncol,
+                                                         double scale, double *out)
+{
+    __shared__ double lds[kBlock / 64][1];
+    const int c = blockIdx.x;
+    double acc[1] = {0.0};
+    for (uint32_t b = threadIdx.x; b < nblk; b += kBlock)
+        acc[0] += partials[(size_t)b * ncol + c];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0)
+        out[c] = acc[0] * scale;
+}
+
+// d_out[0] = mean of the six plane averages d_out[1..6].
+__global__ void plaq_total_kernel(double *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        out[0] = (out[1] + out[2] + out[3] + out[4] + out[5] + out[6]) / 6.0;
+}
+
+__global__ void copy_flags_kernel(const uint32_t *flags, uint32_t *dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *dst = *flags;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+static Geom make_geom(const int32_t n[4])
+{
+    Geom g;
+    for (int d = 0; d < 4; ++d)
+        g.n[d] = n[d];
+    g.nxh = (uint32_t)n[0] / 2u;
+    const uint64_t vol = (uint64_t)n[0] * n[1] * n[2] * n[3];
+    g.half = (uint32_t)(vol / 2);
+    g.vs = (uint32_t)((uint64_t)n[0] * n[1] * n[2]);
+    g.div_nx = make_fastdiv((uint32_t)n[0]);
+    g.div_nxh = make_fastdiv(g.nxh);
+    g.div_ny = make_fastdiv((uint32_t)n[1]);
+    g.div_nz = make_fastdiv((uint32_t)n[2]);
+    return g;
+}
+
+template <class T>
+static Links<T> links_of(const LaunchArgs &a)
+{
+    Links<T> L;
+    L.p = reinterpret_cast<decltype(L.p)>(a.links);
+    L.half = (uint32_t)(a.volume / 2);
+    return L;
+}
+
+static uint32_t blocks_for(uint64_t n)
+{
+    return (uint32_t)((n + kBlock - 1) / kBlock);
+}
+
+template <class T>
+static void launch_hb(const LaunchArgs &a, const Geom &g, int mu, int par, double beta, uint64_t seed,
+                      uint32_t sweep, hipStream_t st)
+{
+    const Links<T> U = links_of<T>(a);
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    const uint32_t c1 = (uint32_t)mu + 4u * 1u + 16u * (uint32_t)a.lattice_id;
+    const dim3 grid(blocks_for(g.half)), block(kBlock);
+    switch (mu) {
+    case 0: heatbath_kernel<T, 0><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, a.flags); break;
+    case 1: heatbath_kernel<T, 1><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, a.flags); break;
+    case 2: heatbath_kernel<T, 2><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, a.flags); break;
+    default: heatbath_kernel<T, 3><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, a.flags); break;
+    }
+}
+
+template <class T>
+static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, hipStream_t st)
+{
+    const Links<T> U = links_of<T>(a);
+    const dim3 grid(blocks_for(g.half)), block(kBlock);
+    switch (mu) {
+    case 0: overrelax_kernel<T, 0><<<grid, block, 0, st>>>(U, g, par, a.flags); break;
+    case 1: overrelax_kernel<T, 1><<<grid, block, 0, st>>>(U, g, par, a.flags); break;
+    case 2: overrelax_kernel<T, 2><<<grid, block, 0, st>>>(U, g, par, a.flags); break;
+    default: overrelax_kernel<T, 3><<<grid, block, 0, st>>>(U, g, par, a.flags); break;
+    }
+}
+
+void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st)
+{
+    const Geom g = make_geom(a.n);
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    const uint32_t lid16 = 16u * (uint32_t)a.lattice_id;
+    const dim3 grid(blocks_for(g.half)), block(kBlock);
+    if (a.prec == kF32)
+        init_kernel<float><<<grid, block, 0, st>>>(links_of<float>(a), g, hot, k0, k1, lid16, a.flags);
+    else
+        init_kernel<double><<<grid, block, 0, st>>>(links_of<double>(a), g, hot, k0, k1, lid16, a.flags);
+}
+
+void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, int mu, int par,
+                     hipStream_t st)
+{
+    const Geom g = make_geom(a.n);
+    if (a.prec == kF32)
+        launch_hb<float>(a, g, mu, par, beta, seed, sweep, st);
+    else
+        launch_hb<double>(a, g, mu, par, beta, seed, sweep, st);
+}
+
+void launch_overrelax(const LaunchArgs &a, int mu, int par, hipStream_t st)
+{
+    const Geom g = make_geom(a.n);
+    if (a.prec == kF32)
+        launch_or<float>(a, g, mu, par, st);
+    else
+        launch_or<double>(a, g, mu, par, st);
+}
+
+void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
+{
+    const Geom g = make_geom(a.n);
+    double *partials = reinterpret_cast<double *>(a.work + w.off_plaq);
+    if (a.prec == kF32)
+        plaquette_kernel<float><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
+    else
+        plaquette_kernel<double><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
+    colsum_kernel<<<6, kBlock, 0, st>>>(partials, w.nblk_plaq, 6, 1.0 / (double)a.volume, d_out + 1);
+    plaq_total_kernel<<<1, 64, 0, st>>>(d_out);
+}
+
+void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st)
+{
+    const Geom g = make_geom(a.n);
+    double *Lf = reinterpret_cast<double *>(a.work + w.off_lfield);
+    double *pp = reinterpret_cast<double *>(a.work + w.off_poly);
+    if (a.prec == kF32)
+        polyakov_kernel<float><<<w.nblk_poly, kBlock, 0, st>>>(links_of<float>(a), g, Lf, pp);
+    else
+        polyakov_kernel<double><<<w.nblk_poly, kBlock, 0, st>>>(links_of<double>(a), g, Lf, pp);
+    colsum_kernel<<<2, kBlock, 0, st>>>(pp, w.nblk_poly, 2, 1.0 / (double)g.vs, d_out);
+    if (d_corr && w.rmax > 0) {
+        double *cp = reinterpret_cast<double *>(a.work + w.off_corr);
+        polycorr_kernel<<<w.nblk_corr, kBlock, 0, st>>>(Lf, g, w.rmax, cp);
+        colsum_kernel<<<w.rmax, kBlock, 0, st>>>(cp, w.nblk_corr, w.rmax, 1.0 / (3.0 * (double)g.vs), d_corr);
+    }
+}
+
+void launch_get_flags(const LaunchArgs &a, uint32_t *d_flags, hipStream_t st)
+{
+    copy_flags_kernel<<<1, 64, 0, st>>>(a.flags, d_flags);
+}
+
+} // namespace su2

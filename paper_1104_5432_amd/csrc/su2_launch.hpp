@@ -1,0 +1,41 @@
+// su2_launch.hpp -- internal interface between the C-ABI facade (argument
+// checks, workspace layout) and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace su2 {
+
+constexpr int kF64 = 0;
+constexpr int kF32 = 1;
+
+// Workspace layout: the flags word, then the reduction partials and the
+// Polyakov-loop field, each region 256-byte aligned.
+struct WorkLayout {
+    uint64_t off_plaq, off_poly, off_corr, off_lfield, total;
+    uint32_t nblk_plaq, nblk_poly, nblk_corr;
+    int rmax;
+};
+
+struct LaunchArgs {
+    int32_t n[4];
+    int prec;
+    int lattice_id;
+    uint64_t volume;
+    void *links;
+    char *work;
+    uint32_t *flags;
+};
+
+WorkLayout work_layout(const int32_t n[4]);
+
+void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st);
+void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, int mu, int par,
+                     hipStream_t st);
+void launch_overrelax(const LaunchArgs &a, int mu, int par, hipStream_t st);
+void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
+void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st);
+void launch_get_flags(const LaunchArgs &a, uint32_t *d_flags, hipStream_t st);
+
+} // namespace su2

@@ -1,0 +1,134 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/su2.h declares, sizes are right, and every argument check rejects a
+bad call before any HIP call (so these run on a machine without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def su2():
+    from paper_1104_5432_amd import build as b
+    if b.is_stale():
+        b.build()
+    import paper_1104_5432_amd as m
+    return m
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "su2.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(su2_\w+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(su2):
+    names = _declared_functions()
+    assert len(names) >= 13
+    raw = ctypes.CDLL(su2.LIB_PATH)
+    for name in names:
+        assert hasattr(raw, name), name
+    # and the binding wraps each of them under the same name
+    for name in names:
+        if name not in ("su2_strerror", "su2_last_error"):
+            assert hasattr(su2, name), name
+
+
+def test_sizes(su2):
+    assert su2.su2_links_bytes((64, 64, 64, 64), "f32") == 64 ** 4 * 4 * 16
+    assert su2.su2_links_bytes((96, 96, 96, 96), "f32") == 96 ** 4 * 4 * 16
+    assert su2.su2_links_bytes((8, 8, 8, 8), "f64") == 8 ** 4 * 4 * 32
+    assert su2.su2_links_bytes((7, 8, 8, 8), "f64") == 0
+    assert su2.lib.su2_links_bytes((ctypes.c_int32 * 4)(8, 8, 8, 8), 5) == 0
+    assert su2.su2_workspace_bytes((64, 64, 64, 64), "f32") > 64 ** 3 * 8
+    assert su2.su2_workspace_bytes((0, 8, 8, 8), "f32") == 0
+    # volume must stay below 2^32 (the site index is the 32-bit Philox counter word)
+    assert su2.su2_links_bytes((256, 256, 256, 256), "f32") == 0
+    assert su2.su2_links_bytes((256, 256, 256, 254), "f32") > 0
+
+
+def _desc(su2, n=(8, 8, 8, 8), prec=0, lid=0, links=0x10000, work=0x20000, wb=None):
+    if wb is None:
+        wb = su2.su2_workspace_bytes(n, 0) if all(v >= 2 and v % 2 == 0 for v in n) else 1 << 20
+    return su2.su2_lattice_t((ctypes.c_int32 * 4)(*n), prec, lid, links, work, wb)
+
+
+def test_argument_checks_reject_before_any_hip_call(su2):
+    L = su2.lib
+    s = None
+    by = ctypes.byref
+    # null descriptor
+    assert L.su2_init_cold(None, s) == su2.SU2_EINVAL
+    # bad precision
+    assert L.su2_init_cold(by(_desc(su2, prec=7)), s) == su2.SU2_EINVAL
+    # extents: odd, too small, volume >= 2^32
+    assert L.su2_init_cold(by(_desc(su2, n=(8, 7, 8, 8))), s) == su2.SU2_EDIMS
+    assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 0, 8))), s) == su2.SU2_EDIMS
+    assert L.su2_init_cold(by(_desc(su2, n=(256, 256, 256, 256))), s) == su2.SU2_EDIMS
+    # lattice id range
+    assert L.su2_init_cold(by(_desc(su2, lid=-1)), s) == su2.SU2_EINVAL
+    assert L.su2_init_cold(by(_desc(su2, lid=1 << 27)), s) == su2.SU2_EINVAL
+    # null and misaligned pointers
+    assert L.su2_init_hot(by(_desc(su2, links=0)), 1, s) == su2.SU2_EINVAL
+    assert L.su2_init_hot(by(_desc(su2, work=0)), 1, s) == su2.SU2_EINVAL
+    assert L.su2_init_hot(by(_desc(su2, links=0x10008)), 1, s) == su2.SU2_EALIGN
+    assert L.su2_init_hot(by(_desc(su2, work=0x20004)), 1, s) == su2.SU2_EALIGN
+    # workspace too small
+    need = su2.su2_workspace_bytes((8, 8, 8, 8), 0)
+    assert L.su2_plaquette(by(_desc(su2, wb=need - 1)), 0x30000, s) == su2.SU2_EWORK
+    # beta
+    ok = by(_desc(su2))
+    for beta in (float("nan"), float("inf"), -0.5):
+        assert L.su2_heatbath_sweep(ok, beta, 1, 0, s) == su2.SU2_EINVAL
+        assert L.su2_heatbath_halfsweep(ok, beta, 1, 0, 0, 0, s) == su2.SU2_EINVAL
+    # class indices
+    assert L.su2_heatbath_halfsweep(ok, 2.3, 1, 0, 4, 0, s) == su2.SU2_EINVAL
+    assert L.su2_heatbath_halfsweep(ok, 2.3, 1, 0, 0, 2, s) == su2.SU2_EINVAL
+    assert L.su2_overrelax_halfsweep(ok, -1, 0, s) == su2.SU2_EINVAL
+    assert L.su2_overrelax_halfsweep(ok, 0, -1, s) == su2.SU2_EINVAL
+    assert L.su2_overrelax(ok, -1, s) == su2.SU2_EINVAL
+    # outputs
+    assert L.su2_plaquette(ok, None, s) == su2.SU2_EINVAL
+    assert L.su2_plaquette(ok, 0x30004, s) == su2.SU2_EALIGN
+    assert L.su2_polyakov(ok, None, None, s) == su2.SU2_EINVAL
+    assert L.su2_polyakov(ok, 0x30000, 0x30003, s) == su2.SU2_EALIGN
+    assert L.su2_get_flags(ok, None, s) == su2.SU2_EINVAL
+    assert L.su2_get_flags(ok, 0x30002, s) == su2.SU2_EALIGN
+    # messages
+    assert L.su2_strerror(su2.SU2_EWORK) == b"workspace too small"
+    assert b"beta" in L.su2_last_error() or len(L.su2_last_error()) > 0
+
+
+def test_binding_raises_on_errors(su2):
+    with pytest.raises(su2.Su2Error):
+        su2.Lattice((8, 7, 8, 8), "f64", device="cpu")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_layout_conversion_matches_documented_layout(su2, prec):
+    import oracle
+    import torch
+    n = (4, 6, 2, 8)
+    U = oracle.init_hot(n, 5)
+    lat = su2.Lattice(n, prec, device="cpu")
+    su2.from_canonical(lat, U)
+    back = su2.to_canonical(lat).numpy()
+    tol = 0 if prec == "f64" else 6e-8
+    assert np.max(np.abs(back - U)) <= tol
+    # the documented layout: plane q = 2 mu + parity, element cb = site / 2
+    nx, ny, nz, nt = n
+    half = int(np.prod(n)) // 2
+    for (x, y, z, t, mu) in [(1, 2, 0, 3, 2), (0, 0, 1, 7, 3), (3, 5, 1, 0, 0)]:
+        site = x + nx * (y + ny * (z + nz * t))
+        q = 2 * mu + (x + y + z + t) % 2
+        cb = site // 2
+        if prec == "f32":
+            v = lat.links.view(torch.float32).view(-1, 4)[q * half + cb].double().numpy()
+        else:
+            d2 = lat.links.view(torch.float64).view(-1, 2)
+            v = np.concatenate([d2[(2 * q) * half + cb].numpy(), d2[(2 * q + 1) * half + cb].numpy()])
+        assert np.max(np.abs(v - U[t, z, y, x, mu])) <= tol

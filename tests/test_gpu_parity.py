@@ -1,0 +1,414 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances:
+- FP64 links: per-link max |dU| <= 1e-12 after up to 5 heat-bath sweeps at
+  beta >= 2.  Both sides compute the same formulas in FP64 from
+  bit-identical uniforms; they differ only by the rounding of
+  log/cos/sin/sqrt and contraction into FMAs (~1e-16), which the chain
+  amplifies: measured with the oracle alone (against a copy perturbed by
+  1e-16), by ~1.45 per heat-bath sweep at beta = 2.3 (1.3e-13 after 5), by
+  5-8 per sweep in the Creutz regime beta < 2, and by 4-10 per
+  overrelaxation sweep.  Chained bounds beyond 1e-12 follow from those
+  factors; every single class and every re-synchronised sweep meets 1e-12.
+- Observables on identical configurations: FP64 sums, <= 1e-13 relative
+  (different, fixed summation orders).
+- FP32 links: after one half-sweep from the same (rounded) configuration,
+  <= 5e-5 per link (FP32 staples, 23-bit uniforms) except links whose
+  accept/reject decision flips between the 23-bit and the 52-bit uniforms.
+- Ensembles (FP32 vs FP64 chains): means within 3 sigma (Gamma-method
+  errors), 2-sigma excursions reported.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from tests import stats_util
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(8, 8, 8, 8), (6, 4, 10, 8), (2, 2, 2, 2), (4, 6, 2, 12), (10, 6, 4, 6)]
+
+
+@pytest.fixture(scope="module")
+def su2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1104_5432_amd as m
+    return m
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+def _lat(su2, n, prec, U=None, lattice_id=0):
+    lat = su2.Lattice(n, prec, device="cuda", lattice_id=lattice_id)
+    if U is not None:
+        su2.from_canonical(lat, U)
+    return lat
+
+
+def _maxdiff(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))))
+
+
+def _flags(su2, lat):
+    f = su2.su2_get_flags(lat)
+    _sync()
+    return int(f.item())
+
+
+# ---------------------------------------------------------------------------
+# starts
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_cold_start_exact(su2, prec):
+    n = (6, 4, 10, 8)
+    lat = _lat(su2, n, prec)
+    su2.su2_init_cold(lat)
+    plaq = su2.su2_plaquette(lat)
+    poly, corr = su2.su2_polyakov(lat)
+    _sync()
+    U = su2.to_canonical(lat).numpy()
+    assert np.array_equal(U, oracle.init_cold(n))
+    assert np.all(plaq.cpu().numpy() == 1.0)
+    assert np.all(poly.cpu().numpy() == 1.0)
+    assert np.all(corr.cpu().numpy() == 1.0)
+    assert _flags(su2, lat) == 0
+
+
+@pytest.mark.parametrize("n", SHAPES)
+def test_hot_start_matches_oracle(su2, n):
+    for lid in (0, 3):
+        ref = oracle.init_hot(n, 1234, lattice_id=lid)
+        lat = _lat(su2, n, "f64", lattice_id=lid)
+        su2.su2_init_hot(lat, 1234)
+        _sync()
+        assert _maxdiff(su2.to_canonical(lat).numpy(), ref) <= 1e-15
+        lat32 = _lat(su2, n, "f32", lattice_id=lid)
+        su2.su2_init_hot(lat32, 1234)
+        _sync()
+        got = su2.to_canonical(lat32).numpy()
+        assert _maxdiff(got, ref) <= 2e-7
+        assert _maxdiff((got * got).sum(-1), 1) <= 3e-7
+
+
+# ---------------------------------------------------------------------------
+# heat bath
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", SHAPES)
+def test_heatbath_halfsweep_each_class(su2, n):
+    beta, seed = 2.3, 77
+    for mu in range(4):
+        for p in range(2):
+            U0 = oracle.init_hot(n, 5 + mu)
+            ref = U0.copy()
+            assert oracle.heatbath_halfsweep(n, ref, beta, seed, 7, mu, p) == 0
+            lat = _lat(su2, n, "f64", U0)
+            su2.su2_heatbath_halfsweep(lat, beta, seed, 7, mu, p)
+            _sync()
+            err = np.max(np.abs(su2.to_canonical(lat).numpy() - ref))
+            assert err <= 1e-13, (n, mu, p, err)
+
+
+@pytest.mark.parametrize("n,beta", [((8, 8, 8, 8), 2.3), ((16, 16, 16, 16), 2.5), ((6, 4, 10, 8), 0.4),
+                                    ((8, 8, 8, 4), 6.0)])
+def test_heatbath_five_sweeps(su2, n, beta):
+    # Chained: the GPU chain against the oracle chain.  For beta >= 2 the
+    # bound is 1e-12 per link.  For beta < 2 (Creutz regime) the chain itself
+    # amplifies differences by ~5-8x per sweep (oracle against a 1e-16
+    # perturbed oracle: 1.6e-11 after 5 sweeps at beta 0.4), so the chained
+    # bound there is 1e-10; re-synchronised single sweeps still meet 1e-12.
+    seed = 1234
+    chain_tol = 1e-12 if beta >= 2 else 1e-10
+    ref = oracle.init_hot(n, seed)
+    lat = _lat(su2, n, "f64")
+    su2.su2_init_hot(lat, seed)
+    for s in range(5):
+        start = ref.copy()
+        assert oracle.heatbath_sweep(n, ref, beta, seed, s) == 0
+        su2.su2_heatbath_sweep(lat, beta, seed, s)
+        one = _lat(su2, n, "f64", start)
+        su2.su2_heatbath_sweep(one, beta, seed, s)
+        _sync()
+        err = np.max(np.abs(su2.to_canonical(lat).numpy() - ref))
+        assert err <= chain_tol, (s, err)
+        err1 = np.max(np.abs(su2.to_canonical(one).numpy() - ref))
+        assert err1 <= 1e-12, (s, err1)
+    assert _flags(su2, lat) == 0
+
+
+def test_paper_workload_plaquette_series(su2):
+    # 8^4, beta 2.3, FP64, hot start seed 1234, 100 heat-bath sweeps, mean
+    # plaquette after every sweep.  Element-wise while the chains have not
+    # decorrelated (first 25 sweeps), statistically over the rest.
+    n, beta, seed = (8, 8, 8, 8), 2.3, 1234
+    ref = oracle.init_hot(n, seed)
+    lat = _lat(su2, n, "f64")
+    su2.su2_init_hot(lat, seed)
+    out = torch.empty((100, 7), dtype=torch.float64, device="cuda")
+    pr = []
+    for s in range(100):
+        su2.su2_heatbath_sweep(lat, beta, seed, s)
+        su2.su2_plaquette(lat, out[s])
+        oracle.heatbath_sweep(n, ref, beta, seed, s)
+        pr.append(oracle.plaquette(n, ref)[0])
+    _sync()
+    pg = out[:, 0].cpu().numpy()
+    pr = np.array(pr)
+    assert _maxdiff(pg[:25], pr[:25]) <= 1e-12
+    mg, eg, _, _ = stats_util.gamma_method(pg[20:])
+    mr, er, _, _ = stats_util.gamma_method(pr[20:])
+    assert abs(mg - mr) <= 3 * np.hypot(eg, er)
+    assert _flags(su2, lat) == 0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("beta", [0.1, 0.3, 2.3, 6.0])
+def test_gpu_single_link_law(su2, prec, beta):
+    # cold start: staple = 6, the first half-sweep draws a0 at alpha = 6 beta
+    n = (16, 16, 16, 16)
+    lat = _lat(su2, n, prec)
+    su2.su2_init_cold(lat)
+    su2.su2_heatbath_halfsweep(lat, beta, 4321, 0, 0, 0)
+    _sync()
+    U = su2.to_canonical(lat).numpy()
+    par = np.add.reduce(np.indices((n[3], n[2], n[1], n[0])), axis=0) % 2
+    x0 = U[par == 0][:, 0, 0]
+    alpha = 6 * beta
+    assert stats.kstest(x0, lambda w: stats_util.x0_cdf(np.full_like(w, alpha), w)).pvalue > 1e-4
+    assert np.all(U[par == 1][:, 0] == [1, 0, 0, 0])
+
+
+def test_fp32_halfsweep_close_to_oracle(su2):
+    n, beta, seed = (8, 8, 8, 8), 2.3, 99
+    U0 = oracle.init_hot(n, 3)
+    for s in range(3):
+        oracle.heatbath_sweep(n, U0, beta, 3, s)
+    lat = _lat(su2, n, "f32", U0)
+    U32 = su2.to_canonical(lat).numpy()           # the FP32-rounded start
+    ref = U32.copy()
+    oracle.heatbath_halfsweep(n, ref, beta, seed, 4, 1, 0)
+    su2.su2_heatbath_halfsweep(lat, beta, seed, 4, 1, 0)
+    _sync()
+    d = np.max(np.abs(su2.to_canonical(lat).numpy() - ref), axis=-1)
+    assert np.mean(d > 5e-5) <= 1e-3, np.sort(d.ravel())[-5:]
+
+
+# ---------------------------------------------------------------------------
+# overrelaxation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", SHAPES)
+def test_overrelax_matches_oracle(su2, n):
+    # Overrelaxation is deterministic and chaotic: oracle against a 1e-16
+    # perturbed oracle differs by ~2e-12 after 4 sweeps (growth 4-10x per
+    # sweep).  Single classes and re-synchronised sweeps meet 1e-13; the
+    # chained 4-sweep bound is 1e-10.
+    U0 = oracle.init_hot(n, 44)
+    for s in range(2):
+        oracle.heatbath_sweep(n, U0, 2.3, 44, s)
+    ref = U0.copy()
+    lat = _lat(su2, n, "f64", U0)
+    oracle.overrelax_halfsweep(n, ref, 2, 1)
+    su2.su2_overrelax_halfsweep(lat, 2, 1)
+    _sync()
+    assert _maxdiff(su2.to_canonical(lat).numpy(), ref) <= 1e-14
+    for _ in range(4):
+        start = ref.copy()
+        oracle.overrelax_sweep(n, ref)
+        one = _lat(su2, n, "f64", start)
+        su2.su2_overrelax(one, 1)
+        su2.su2_overrelax(lat, 1)
+        _sync()
+        assert _maxdiff(su2.to_canonical(one).numpy(), ref) <= 1e-13
+    assert _maxdiff(su2.to_canonical(lat).numpy(), ref) <= 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 2e-5)])
+def test_overrelax_invariants_on_gpu(su2, prec, tol):
+    n = (8, 8, 8, 8)
+    lat = _lat(su2, n, prec)
+    su2.su2_init_hot(lat, 8)
+    for s in range(3):
+        su2.su2_heatbath_sweep(lat, 2.3, 8, s)
+    p0 = su2.su2_plaquette(lat).clone()
+    before = su2.to_canonical(lat).numpy()
+    su2.su2_overrelax_halfsweep(lat, 1, 0)
+    p1 = su2.su2_plaquette(lat).clone()
+    su2.su2_overrelax_halfsweep(lat, 1, 0)
+    _sync()
+    assert abs(p1[0].item() - p0[0].item()) <= tol
+    assert _maxdiff(su2.to_canonical(lat).numpy(), before) <= (1e-14 if prec == "f64" else 3e-6)
+    su2.su2_overrelax(lat, 3)
+    p2 = su2.su2_plaquette(lat)
+    _sync()
+    assert abs(p2[0].item() - p0[0].item()) <= 5 * tol
+
+
+# ---------------------------------------------------------------------------
+# observables on identical configurations
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", SHAPES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_observables_match_oracle(su2, n, prec):
+    U0 = oracle.init_hot(n, 61)
+    for s in range(3):
+        oracle.heatbath_sweep(n, U0, 2.4, 61, s)
+    lat = _lat(su2, n, prec, U0)
+    Uc = su2.to_canonical(lat).numpy()            # exactly what the GPU holds
+    plaq = su2.su2_plaquette(lat)
+    poly, corr = su2.su2_polyakov(lat)
+    _sync()
+    p, planes = oracle.plaquette(n, Uc)
+    l_mean, l_abs = oracle.polyakov(n, Uc)
+    C = oracle.polyakov_corr(n, Uc)
+    # FP64: only summation order differs.  FP32: products of FP32 links.
+    tol = 1e-13 if prec == "f64" else 2e-6
+    g = plaq.cpu().numpy()
+    assert abs(g[0] - p) <= tol and np.max(np.abs(g[1:] - planes)) <= tol
+    g = poly.cpu().numpy()
+    assert abs(g[0] - l_mean) <= tol and abs(g[1] - l_abs) <= tol
+    assert _maxdiff(corr.cpu().numpy()[:len(C)], C) <= tol
+
+
+def test_observables_gauge_invariant_on_gpu(su2):
+    n = (8, 6, 4, 6)
+    U0 = oracle.init_hot(n, 17)
+    for s in range(3):
+        oracle.heatbath_sweep(n, U0, 2.3, 17, s)
+    G = U0.copy()
+    oracle.gauge_transform(n, G, 555)
+    a, b = _lat(su2, n, "f64", U0), _lat(su2, n, "f64", G)
+    pa, pb = su2.su2_plaquette(a), su2.su2_plaquette(b)
+    (la, ca), (lb, cb) = su2.su2_polyakov(a), su2.su2_polyakov(b)
+    _sync()
+    assert torch.max(torch.abs(pa - pb)).item() <= 1e-13
+    assert torch.max(torch.abs(la - lb)).item() <= 1e-13
+    assert torch.max(torch.abs(ca - cb)).item() <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# full size (64^4), the configuration the benchmark times
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_64(su2, prec):
+    n, beta, seed = (64, 64, 64, 64), 2.3, 1234
+    print(f"full-size parity {n} {prec}", flush=True)
+    ref = oracle.init_hot(n, seed)
+    lat = _lat(su2, n, prec)
+    su2.su2_init_hot(lat, seed)
+    _sync()
+    tol_start = 1e-15 if prec == "f64" else 2e-7
+    assert _maxdiff(su2.to_canonical(lat).numpy(), ref) <= tol_start
+    if prec == "f32":
+        ref = su2.to_canonical(lat).numpy()
+    # one heat-bath class with the t wrap-around, one overrelaxation class
+    oracle.heatbath_halfsweep(n, ref, beta, seed, 0, 3, 1)
+    su2.su2_heatbath_halfsweep(lat, beta, seed, 0, 3, 1)
+    oracle.overrelax_halfsweep(n, ref, 0, 0)
+    su2.su2_overrelax_halfsweep(lat, 0, 0)
+    plaq = su2.su2_plaquette(lat)
+    poly, corr = su2.su2_polyakov(lat)
+    _sync()
+    got = su2.to_canonical(lat).numpy()
+    d = np.max(np.abs(got - ref), axis=-1)
+    if prec == "f64":
+        assert d.max() <= 1e-13
+    else:
+        assert np.mean(d > 5e-5) <= 1e-4 and np.median(d) < 1e-6
+    del ref
+    p, planes = oracle.plaquette(n, got)
+    lm, la = oracle.polyakov(n, got)
+    tol = 1e-13 if prec == "f64" else 1e-6
+    g = plaq.cpu().numpy()
+    assert abs(g[0] - p) <= tol and np.max(np.abs(g[1:] - planes)) <= tol
+    g = poly.cpu().numpy()
+    assert abs(g[0] - lm) <= tol and abs(g[1] - la) <= tol
+    assert _flags(su2, lat) == 0
+
+
+# ---------------------------------------------------------------------------
+# determinism, resume, failure flags
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bitwise_determinism_and_resume(su2, prec):
+    n = (8, 8, 8, 8)
+    a, b = _lat(su2, n, prec), _lat(su2, n, prec)
+    for lat in (a, b):
+        su2.su2_init_hot(lat, 1234)
+        for s in range(2):
+            su2.su2_heatbath_sweep(lat, 2.3, 1234, s)
+            su2.su2_overrelax(lat, 2)
+    _sync()
+    assert torch.equal(a.links, b.links)
+    c = _lat(su2, n, prec)
+    c.links.copy_(a.links)                    # checkpoint = links + next sweep index
+    for lat in (a, c):
+        for s in range(2, 4):
+            su2.su2_heatbath_sweep(lat, 2.3, 1234, s)
+            su2.su2_overrelax(lat, 2)
+    pa, pc = su2.su2_plaquette(a), su2.su2_plaquette(c)
+    _sync()
+    assert torch.equal(a.links, c.links) and torch.equal(pa, pc)
+
+
+def test_nonfinite_link_sets_flag(su2):
+    n = (4, 4, 4, 4)
+    U = oracle.init_hot(n, 3)
+    U[0, 0, 0, 1, 1] = [np.nan, 0, 0, 0]
+    lat = _lat(su2, n, "f64", U)
+    assert _flags(su2, lat) == 0
+    su2.su2_heatbath_halfsweep(lat, 2.3, 3, 0, 0, 0)
+    _sync()
+    assert _flags(su2, lat) & su2.SU2_FLAG_NONFINITE
+    got = su2.to_canonical(lat).numpy()
+    assert np.array_equal(got[0, 0, 0, 0, 0], U[0, 0, 0, 0, 0])   # kept
+    su2.su2_init_cold(lat)
+    assert _flags(su2, lat) == 0
+
+
+def test_streams_order_work(su2):
+    n = (8, 8, 8, 8)
+    s = torch.cuda.Stream()
+    lat = _lat(su2, n, "f64")
+    with torch.cuda.stream(s):
+        su2.su2_init_hot(lat, 9, stream=s)
+        su2.su2_heatbath_sweep(lat, 2.3, 9, 0, stream=s)
+        out = su2.su2_plaquette(lat, stream=s)
+    s.synchronize()
+    ref = oracle.init_hot(n, 9)
+    oracle.heatbath_sweep(n, ref, 2.3, 9, 0)
+    assert abs(out[0].item() - oracle.plaquette(n, ref)[0]) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# FP32 against FP64 ensembles
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("beta,n", [(2.3, (12, 12, 12, 12)), (2.5, (16, 16, 16, 4))])
+def test_fp32_ensemble_matches_fp64(su2, beta, n):
+    nsw, therm = 500, 100
+    series = {}
+    for prec in ("f64", "f32"):
+        lat = _lat(su2, n, prec)
+        su2.su2_init_hot(lat, 2011)
+        out = torch.empty((nsw, 7), dtype=torch.float64, device="cuda")
+        pol = torch.empty((nsw, 2), dtype=torch.float64, device="cuda")
+        for s in range(nsw):
+            su2.su2_heatbath_sweep(lat, beta, 2011 + (prec == "f32"), s)
+            su2.su2_overrelax(lat, 4)
+            su2.su2_plaquette(lat, out[s])
+            su2.su2_polyakov(lat, pol[s], with_corr=False)
+        _sync()
+        assert _flags(su2, lat) == 0
+        U = su2.to_canonical(lat).numpy()
+        assert _maxdiff((U * U).sum(-1), 1) <= (1e-14 if prec == "f64" else 1e-6)
+        series[prec] = (out[therm:, 0].cpu().numpy(), np.abs(pol[therm:, 0].cpu().numpy()))
+    for k, name in enumerate(("plaquette", "|L|")):
+        m64, e64, _, _ = stats_util.gamma_method(series["f64"][k])
+        m32, e32, _, _ = stats_util.gamma_method(series["f32"][k])
+        z = (m32 - m64) / np.hypot(e64, e32)
+        print(f"{name}: f64 {m64:.6f}({e64:.6f}) f32 {m32:.6f}({e32:.6f}) z = {z:+.2f}", flush=True)
+        assert abs(z) <= 3.0
