@@ -169,6 +169,23 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
     return (__umulhi(n, f.m) + n) >> f.l;
 }
 
+// Order in which the blocks of one checkerboard class walk the lattice.
+// A block covers 256 consecutive cb indices.  In strip mode (used when a
+// (z,t) column of C = Nx*Ny/2 cb indices is a whole number S of blocks and
+// the strip width W divides Nz), columns are visited strip by strip of W
+// z-values, t-major inside a strip: the +-t neighbours of a column are then
+// W columns away in dispatch order and still in the XCD's L2, instead of a
+// whole t-slice away.  Mode 0 is plain cb order.  Every order is a bijection
+// onto the blocks, so results do not depend on it.
+struct BlockOrder {
+    uint32_t strip;      // 0 = linear, else W
+    uint32_t cols;       // C = cb indices per (z,t) column
+    uint32_t nz;         // Nz
+    FastDiv div_s;       // by S = C / 256
+    FastDiv div_w;       // by W
+    FastDiv div_nt;      // by Nt
+};
+
 // ---------------------------------------------------------------------------
 // Geometry: periodic Nx x Ny x Nz x Nt, x fastest, checkerboard index
 // cb = site/2; a "row" is a line of constant (y,z,t): row = y + Ny(z + Nz t).
@@ -179,6 +196,7 @@ struct Geom {
     uint32_t half; // V/2
     uint32_t vs;   // Nx Ny Nz
     FastDiv div_nx, div_nxh, div_ny, div_nz;
+    BlockOrder ord;
 };
 
 struct Site {
@@ -288,6 +306,22 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks)
     const uint32_t q = nblocks >> 3, r = nblocks & 7u;
     const uint32_t xcd = b & 7u, k = b >> 3;
     return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+// First cb index of the block handled by hardware block b of nblocks.
+__device__ __forceinline__ uint32_t block_base(uint32_t b, uint32_t nblocks, const BlockOrder &o)
+{
+    const uint32_t k = xcd_tile(b, nblocks);
+    if (o.strip == 0)
+        return k * 256u;
+    const uint32_t j = fdiv(k, o.div_s);
+    const uint32_t sub = k - j * o.div_s.d;
+    const uint32_t q = fdiv(j, o.div_w);
+    const uint32_t zz = j - q * o.strip;
+    const uint32_t s = fdiv(q, o.div_nt);
+    const uint32_t t = q - s * o.div_nt.d;
+    const uint32_t z = s * o.strip + zz;
+    return sub * 256u + o.cols * (z + o.nz * t);
 }
 
 } // namespace su2

@@ -7,6 +7,8 @@
 #include "su2_device.hpp"
 #include "su2_launch.hpp"
 
+#include <cstdlib>
+
 namespace su2 {
 
 constexpr int kBlock = 256;
@@ -52,76 +54,215 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, cons
 // new link is W Vhat^dagger where W has density ~ exp(alpha w0) w.r.t. Haar
 // measure: w0 by Kennedy-Pendleton (alpha >= 2) or Creutz (alpha < 2), the
 // vector part isotropic with length sqrt(1 - w0^2).  Random numbers: counter
-// (site, c1, sweep, 4*attempt + draw); draws 0,1 feed the sampler attempt,
-// draw 2 (of attempt 0) the direction.  The sampler runs in FP64 for both
-// link precisions.
+// (site, c1, sweep, 4*attempt + draw); draws 0,1 feed sampler attempt
+// `attempt`, draw 2 (of attempt 0) the direction.
+//
+// One attempt of the sampler.  FP64 links: everything in FP64.  FP32 links:
+// uniforms from 23 bits, the logarithms and cosines in FP32, and lambda^2,
+// the accept test, x0 = 1 - 2 lambda^2 and |x| = 2 sqrt(lambda^2 (1 -
+// lambda^2)) assembled in FP64; lambda^2 carries 1 - x0 directly, so x0 near
+// 1 suffers no cancellation.  The Creutz branch (alpha < 2) is FP64 for both.
 // ---------------------------------------------------------------------------
+template <class T>
+struct KP;
+
+template <>
+struct KP<double> {
+    __device__ static __forceinline__ bool attempt(double inv2a, uint32_t site, uint32_t c1, uint32_t sweep,
+                                                   uint32_t a, uint32_t k0, uint32_t k1, double &x0,
+                                                   double &xlen)
+    {
+        double u1, u2, u3, u4;
+        Draw<double>::two(philox(site, c1, sweep, 4u * a, k0, k1), u1, u2);
+        Draw<double>::two(philox(site, c1, sweep, 4u * a + 1u, k0, k1), u3, u4);
+        const double c = cos((2.0 * kPi) * u2);
+        const double lam2 = -(log(u1) + c * c * log(u3)) * inv2a;
+        if (lam2 <= 1.0 && u4 * u4 <= 1.0 - lam2) {
+            x0 = 1.0 - 2.0 * lam2;
+            xlen = 2.0 * sqrt(lam2 * (1.0 - lam2));
+            return true;
+        }
+        return false;
+    }
+};
+
+template <>
+struct KP<float> {
+    __device__ static __forceinline__ bool attempt(double inv2a, uint32_t site, uint32_t c1, uint32_t sweep,
+                                                   uint32_t a, uint32_t k0, uint32_t k1, double &x0,
+                                                   double &xlen)
+    {
+        const U32x4 ra = philox(site, c1, sweep, 4u * a, k0, k1);
+        const U32x4 rb = philox(site, c1, sweep, 4u * a + 1u, k0, k1);
+        const float u1 = u01_f32(ra.r0), u2 = u01_f32(ra.r2);
+        const float u3 = u01_f32(rb.r0), u4 = u01_f32(rb.r2);
+        const float c = cospif(2.0f * u2);
+        const double lam2 = -((double)logf(u1) + (double)(c * c) * (double)logf(u3)) * inv2a;
+        const double u4d = (double)u4;
+        if (lam2 <= 1.0 && u4d * u4d <= 1.0 - lam2) {
+            x0 = 1.0 - 2.0 * lam2;
+            xlen = 2.0 * sqrt(lam2 * (1.0 - lam2));
+            return true;
+        }
+        return false;
+    }
+};
+
+template <class T>
+__device__ __forceinline__ bool creutz_attempt(double alpha, uint32_t site, uint32_t c1, uint32_t sweep,
+                                               uint32_t a, uint32_t k0, uint32_t k1, double &x0, double &xlen)
+{
+    double u1, u2;
+    Draw<T>::two(philox(site, c1, sweep, 4u * a, k0, k1), u1, u2);
+    double t;
+    if (alpha < 1e-8) {
+        t = 2.0 * u1 - 1.0;
+    } else {
+        const double e = exp(-2.0 * alpha);
+        t = 1.0 + log(e + u1 * (1.0 - e)) / alpha;
+    }
+    if (u2 * u2 <= 1.0 - t * t) {
+        x0 = t;
+        xlen = sqrt(fmax(0.0, 1.0 - t * t));
+        return true;
+    }
+    return false;
+}
+
+template <class T>
+__device__ __forceinline__ bool sampler_attempt(double alpha, double inv2a, uint32_t site, uint32_t c1,
+                                                uint32_t sweep, uint32_t a, uint32_t k0, uint32_t k1, double &x0,
+                                                double &xlen)
+{
+    if (alpha >= 2.0)
+        return KP<T>::attempt(inv2a, site, c1, sweep, a, k0, k1, x0, xlen);
+    return creutz_attempt<T>(alpha, site, c1, sweep, a, k0, k1, x0, xlen);
+}
+
+// Direction of the vector part: cos(theta) = 2 u5 - 1, phi = 2 pi u6.
+template <class T>
+struct Direction;
+
+template <>
+struct Direction<double> {
+    __device__ static __forceinline__ Quat<double> make(double x0, double xlen, const U32x4 &r)
+    {
+        double u5, u6;
+        Draw<double>::two(r, u5, u6);
+        const double cth = 2.0 * u5 - 1.0;
+        const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
+        double sph, cph;
+        sincos((2.0 * kPi) * u6, &sph, &cph);
+        return {x0, xlen * sth * cph, xlen * sth * sph, xlen * cth};
+    }
+};
+
+template <>
+struct Direction<float> {
+    __device__ static __forceinline__ Quat<float> make(double x0, double xlen, const U32x4 &r)
+    {
+        const float u5 = u01_f32(r.r0), u6 = u01_f32(r.r2);
+        const float cth = 2.0f * u5 - 1.0f;
+        const float sth = sqrtf(fmaxf(0.0f, 1.0f - cth * cth));
+        float sph, cph;
+        sincospif(2.0f * u6, &sph, &cph);
+        const float xl = (float)xlen;
+        return {(float)x0, xl * sth * cph, xl * sth * sph, xl * cth};
+    }
+};
+
+// The kernel.  Every lane first tries attempt 0.  Lanes that reject (a few
+// per cent at equilibrium) are compacted block-wide through LDS (wave
+// ballots, no atomics) and retried by as few lanes as there are rejections,
+// so a wave64 no longer idles until its slowest lane accepts.  A link's
+// attempt sequence, and so its result, does not depend on which lane runs it.
 template <class T, int MU>
 __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, int par, double beta,
                                                            uint32_t k0, uint32_t k1, uint32_t c1,
                                                            uint32_t sweep, uint32_t *flags)
 {
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t cb = tile * kBlock + threadIdx.x;
-    if (cb >= g.half)
-        return;
-    const Site s = site_of_cb(g, cb, par);
-    const Quat<T> V = staple<T, MU>(U, g, s, cb, par);
-    const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
-    const T k = sqrt(k2);
-    if (!isfinite(k)) {
-        atomicOr(flags, kFlagNonFinite);
-        return;
-    }
-    Quat<T> Vh = {1, 0, 0, 0};
-    if (k > T(0)) {
-        const T inv = T(1) / k;
-        Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
-    }
-    const double alpha = beta * (double)k;
+    __shared__ uint32_t s_queue[kBlock];
+    __shared__ uint32_t s_site[kBlock];
+    __shared__ double s_alpha[kBlock];
+    __shared__ double s_x0[kBlock];
+    __shared__ double s_xlen[kBlock];
+    __shared__ uint32_t s_wcount[kBlock / 64];
 
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cb = block_base(blockIdx.x, gridDim.x, g.ord) + tid;
+    const bool valid = cb < g.half;
+
+    Site s = {};
+    Quat<T> Vh = {1, 0, 0, 0};
+    double alpha = 0.0;
+    bool need = false;
+    if (valid) {
+        s = site_of_cb(g, cb, par);
+        const Quat<T> V = staple<T, MU>(U, g, s, cb, par);
+        const T k = sqrt(V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z);
+        if (!isfinite(k)) {
+            atomicOr(flags, kFlagNonFinite);
+        } else {
+            if (k > T(0)) {
+                const T inv = T(1) / k;
+                Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
+            }
+            alpha = beta * (double)k;
+            need = true;
+        }
+    }
+    const double inv2a = 1.0 / (2.0 * fmax(alpha, 1.0));
+
+    // attempt 0 on every lane
     double x0 = 0.0, xlen = 0.0;
     bool ok = false;
-    if (alpha >= 2.0) {
-        const double inv2a = 1.0 / (2.0 * alpha);
-        for (uint32_t a = 0; a < kMaxAttempts; ++a) {
-            double u1, u2, u3, u4;
-            Draw<T>::two(philox(s.site, c1, sweep, 4u * a, k0, k1), u1, u2);
-            Draw<T>::two(philox(s.site, c1, sweep, 4u * a + 1u, k0, k1), u3, u4);
-            const double c = cos((2.0 * kPi) * u2);
-            const double lam2 = -(log(u1) + c * c * log(u3)) * inv2a;
-            if (lam2 <= 1.0 && u4 * u4 <= 1.0 - lam2) {
-                x0 = 1.0 - 2.0 * lam2;
-                xlen = 2.0 * sqrt(lam2 * (1.0 - lam2));
-                ok = true;
-                break;
-            }
-        }
-    } else {
-        const double e = exp(-2.0 * alpha);
-        for (uint32_t a = 0; a < kMaxAttempts; ++a) {
-            double u1, u2;
-            Draw<T>::two(philox(s.site, c1, sweep, 4u * a, k0, k1), u1, u2);
-            const double t = (alpha < 1e-8) ? 2.0 * u1 - 1.0 : 1.0 + log(e + u1 * (1.0 - e)) / alpha;
-            if (u2 * u2 <= 1.0 - t * t) {
-                x0 = t;
-                xlen = sqrt(fmax(0.0, 1.0 - t * t));
-                ok = true;
-                break;
-            }
-        }
+    if (need)
+        ok = sampler_attempt<T>(alpha, inv2a, s.site, c1, sweep, 0u, k0, k1, x0, xlen);
+    const bool retry = need && !ok;
+
+    // compact the rejected lanes of the block
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint64_t mask = __ballot(retry);
+    if (retry) {
+        const uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
+        s_queue[wave * 64u + rank] = tid;
+        s_site[tid] = s.site;
+        s_alpha[tid] = alpha;
     }
-    if (!ok) {
-        atomicOr(flags, kFlagCap);
+    if (lane == 0)
+        s_wcount[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint32_t total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w)
+        total += s_wcount[w];
+    for (uint32_t i = tid; i < total; i += kBlock) {
+        uint32_t w = 0, r = i;
+        while (r >= s_wcount[w]) {
+            r -= s_wcount[w];
+            ++w;
+        }
+        const uint32_t src = s_queue[w * 64u + r];
+        const double a_src = s_alpha[src];
+        const double inv2a_src = 1.0 / (2.0 * fmax(a_src, 1.0));
+        double qx0 = 0.0, qxl = -1.0;
+        for (uint32_t a = 1; a < kMaxAttempts; ++a)
+            if (sampler_attempt<T>(a_src, inv2a_src, s_site[src], c1, sweep, a, k0, k1, qx0, qxl))
+                break;
+        s_x0[src] = qx0;
+        s_xlen[src] = qxl;
+    }
+    __syncthreads();
+    if (retry) {
+        x0 = s_x0[tid];
+        xlen = s_xlen[tid];
+        ok = xlen >= 0.0;
+        if (!ok)
+            atomicOr(flags, kFlagCap);
+    }
+    if (!ok)
         return;
-    }
-    double u5, u6;
-    Draw<T>::two(philox(s.site, c1, sweep, 2u, k0, k1), u5, u6);
-    const double cth = 2.0 * u5 - 1.0;
-    const double sth = sqrt(fmax(0.0, 1.0 - cth * cth));
-    double sph, cph;
-    sincos((2.0 * kPi) * u6, &sph, &cph);
-    const Quat<T> X = {(T)x0, (T)(xlen * sth * cph), (T)(xlen * sth * sph), (T)(xlen * cth)};
+    const Quat<T> X = Direction<T>::make(x0, xlen, philox(s.site, c1, sweep, 2u, k0, k1));
     U.st(MU, par, cb, unitize(qmul_nd(X, Vh)));
 }
 
@@ -131,8 +272,7 @@ __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, in
 template <class T, int MU>
 __global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags)
 {
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t cb = tile * kBlock + threadIdx.x;
+    const uint32_t cb = block_base(blockIdx.x, gridDim.x, g.ord) + threadIdx.x;
     if (cb >= g.half)
         return;
     const Site s = site_of_cb(g, cb, par);
@@ -225,37 +365,40 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[NV])
     }
 }
 
-// Plaquettes: every site x (both parities) sums (1/2) Tr of its six
-// plaquettes U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+, mu < nu, in FP64.
+// Plaquettes: every site x sums (1/2) Tr of its six plaquettes
+// U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+, mu < nu, in FP64.  A thread
+// takes one cb index and both parities; blocks walk the lattice in the
+// same order as the update kernels; one partial per block.
 template <class T>
 __global__ __launch_bounds__(kBlock) void plaquette_kernel(Links<T> U, Geom g, double *partials)
 {
     __shared__ double lds[kBlock / 64][6];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    const uint32_t total = 2u * g.half;
-    for (uint32_t idx = blockIdx.x * kBlock + threadIdx.x; idx < total; idx += gridDim.x * kBlock) {
-        const int par = idx >= g.half;
-        const uint32_t cb = idx - (par ? g.half : 0u);
-        const int opp = par ^ 1;
-        const Site s = site_of_cb(g, cb, par);
-        Quat<T> own[4];
+    const uint32_t cb = block_base(blockIdx.x, gridDim.x, g.ord) + threadIdx.x;
+    if (cb < g.half) {
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu)
-            own[mu] = U.ld(mu, par, cb);
-        uint32_t cbp[4];
-        cbp[0] = cb_shift(g, s.c, 1, 0, 0, 0);
-        cbp[1] = cb_shift(g, s.c, 0, 1, 0, 0);
-        cbp[2] = cb_shift(g, s.c, 0, 0, 1, 0);
-        cbp[3] = cb_shift(g, s.c, 0, 0, 0, 1);
-        int p = 0;
+        for (int par = 0; par < 2; ++par) {
+            const int opp = par ^ 1;
+            const Site s = site_of_cb(g, cb, par);
+            Quat<T> own[4];
 #pragma unroll
-        for (int mu = 0; mu < 4; ++mu)
+            for (int mu = 0; mu < 4; ++mu)
+                own[mu] = U.ld(mu, par, cb);
+            uint32_t cbp[4];
+            cbp[0] = cb_shift(g, s.c, 1, 0, 0, 0);
+            cbp[1] = cb_shift(g, s.c, 0, 1, 0, 0);
+            cbp[2] = cb_shift(g, s.c, 0, 0, 1, 0);
+            cbp[3] = cb_shift(g, s.c, 0, 0, 0, 1);
+            int p = 0;
 #pragma unroll
-            for (int nu = mu + 1; nu < 4; ++nu) {
-                const Quat<T> a = qmul(own[mu], U.ld(nu, opp, cbp[mu]));
-                const Quat<T> b = qmul(own[nu], U.ld(mu, opp, cbp[nu]));
-                acc[p++] += (double)qdot(a, b);
-            }
+            for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+                for (int nu = mu + 1; nu < 4; ++nu) {
+                    const Quat<T> a = qmul(own[mu], U.ld(nu, opp, cbp[mu]));
+                    const Quat<T> b = qmul(own[nu], U.ld(mu, opp, cbp[nu]));
+                    acc[p++] += (double)qdot(a, b);
+                }
+        }
     }
     block_sum<6>(acc, lds);
     if (threadIdx.x == 0)
@@ -350,6 +493,32 @@ __global__ void copy_flags_kernel(const uint32_t *flags, uint32_t *dst)
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+// Strip width of the block order: SU2_STRIP_WIDTH if set (0 = plain cb
+// order), else Nz/8 rounded down to a divisor of Nz, so that the eight XCDs
+// each take one strip range.  Strips need whole blocks per (z,t) column.
+static BlockOrder make_block_order(const int32_t n[4])
+{
+    BlockOrder o = {};
+    const uint32_t cols = (uint32_t)n[0] / 2u * (uint32_t)n[1];
+    const uint32_t nz = (uint32_t)n[2];
+    o.cols = cols;
+    o.nz = nz;
+    if (cols % kBlock != 0)
+        return o;
+    uint32_t w = nz / 8u > 0 ? nz / 8u : 1u;
+    if (const char *env = getenv("SU2_STRIP_WIDTH"))
+        w = (uint32_t)atoi(env);
+    if (w == 0)
+        return o;
+    while (nz % w)
+        --w;
+    o.strip = w;
+    o.div_s = make_fastdiv(cols / kBlock);
+    o.div_w = make_fastdiv(w);
+    o.div_nt = make_fastdiv((uint32_t)n[3]);
+    return o;
+}
+
 static Geom make_geom(const int32_t n[4])
 {
     Geom g;
@@ -363,6 +532,7 @@ static Geom make_geom(const int32_t n[4])
     g.div_nxh = make_fastdiv(g.nxh);
     g.div_ny = make_fastdiv((uint32_t)n[1]);
     g.div_nz = make_fastdiv((uint32_t)n[2]);
+    g.ord = make_block_order(n);
     return g;
 }
 

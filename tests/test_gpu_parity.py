@@ -29,7 +29,11 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(8, 8, 8, 8), (6, 4, 10, 8), (2, 2, 2, 2), (4, 6, 2, 12), (10, 6, 4, 6)]
+# (16, 32, 8, 4) and (32, 16, 8, 2) have whole 256-site blocks per (z,t) column and
+# so run in the strip block order; the others run in plain cb order with a
+# ragged last block.
+SHAPES = [(8, 8, 8, 8), (6, 4, 10, 8), (2, 2, 2, 2), (4, 6, 2, 12), (10, 6, 4, 6), (16, 32, 8, 4),
+          (32, 16, 8, 2)]
 
 
 @pytest.fixture(scope="module")
@@ -333,6 +337,26 @@ def test_full_size_64(su2, prec):
 # ---------------------------------------------------------------------------
 # determinism, resume, failure flags
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_block_order_does_not_change_results(su2, prec, monkeypatch):
+    # links of one class are independent, so every block order must give
+    # bit-identical links; plaquette sums differ only in summation order
+    n = (32, 16, 8, 4)
+    links, plaqs = [], []
+    for w in ("0", "1", "2", "4", "8"):
+        monkeypatch.setenv("SU2_STRIP_WIDTH", w)
+        lat = _lat(su2, n, prec)
+        su2.su2_init_hot(lat, 5)
+        su2.su2_heatbath_sweep(lat, 2.3, 5, 0)
+        su2.su2_overrelax(lat, 2)
+        plaqs.append(su2.su2_plaquette(lat).clone())
+        _sync()
+        links.append(lat.links.clone())
+    for k in range(1, len(links)):
+        assert torch.equal(links[0], links[k])
+        assert torch.max(torch.abs(plaqs[0] - plaqs[k])).item() <= 1e-15
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_bitwise_determinism_and_resume(su2, prec):
     n = (8, 8, 8, 8)
