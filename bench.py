@@ -42,6 +42,35 @@ def parse():
     return ap.parse_args()
 
 
+def csrc_sha256():
+    """Hash of the kernel sources, to tell whether a stored counter profile is current."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", "*"))):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel, prec, shape):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summaries under profiles/ (copy-calibrated), or None when no summary was
+    taken from the current kernel sources."""
+    import glob
+    want = {"kernel": kernel, "prec": prec, "shape": shape, "csrc_sha256": csrc_sha256()}
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(item.split("=", 1) for item in line.split()[1:])
+                if all(kv.get(k) == v for k, v in want.items()):
+                    return float(kv["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(shape, beta, seed, n_or):
     """The FP64 CPU oracle timed on a bounded sample of the same workload."""
     import numpy as np  # noqa: F401
@@ -173,7 +202,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": or_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": profiled_traffic("overrelax_kernel", args.prec, args.shape),
             "bytes_per_launch": or_bytes,
             "avg_launch_ms": or_launch_ms,
         },
@@ -182,6 +211,7 @@ def main():
             "achieved": hb_gbs,
             "frac": hb_gbs / HBM_PEAK_GBS,
             "bytes_per_launch": hb_bytes,
+            "traffic": profiled_traffic("heatbath_kernel", args.prec, args.shape),
             "avg_launch_ms": hb_launch_ms,
         },
         "sweep_roofline_frac": ((hb_bytes * 8 + or_bytes * 8 * args.or_per_hb) / ((hb_ms + or_ms) * 1e-3) / 1e9)
