@@ -36,6 +36,14 @@ def parse():
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-shape", type=str, default="48,48,48,48")
+    ap.add_argument("--start", choices=["hot", "cold"], default="hot")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="walk of the single lattice: 0 default strip, > 0 strip width, < 0 plain order")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the walk with paper_1104_5432_amd.autotune before timing (untimed)")
+    ap.add_argument("--workload", choices=["single", "scan"], default="single",
+                    help="single: one lattice (--shape); scan: 16 lattices mixing 32^3x4, 48^3x6, "
+                         "64^3x8 at beta 2.2..2.7, one captured graph replay per sweep")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="bytes of a plain device copy to run before the timed region "
                          "(reference for hardware byte counters)")
@@ -96,12 +104,97 @@ def cpu_baseline(shape, beta, seed, n_or):
     }
 
 
+def scan(args):
+    """Finite-temperature scan: 16 independent lattices, shapes cycling over
+    32^3x4, 48^3x6, 64^3x8, beta_j = 2.2 + 0.5 j/15, lattice_id j, one
+    captured graph per sweep (batched heat bath reading the sweep index from
+    device memory, args.or_per_hb batched overrelaxation sweeps, Polyakov
+    loop and correlator of every lattice, sweep advance)."""
+    import torch
+    import paper_1104_5432_amd as su2
+
+    shapes = [(32, 32, 32, 4), (48, 48, 48, 6), (64, 64, 64, 8)]
+    lats, betas = [], []
+    for j in range(16):
+        lat = su2.Lattice(shapes[j % 3], args.prec, device="cuda:0", lattice_id=j)
+        su2.su2_init_hot(lat, args.seed)
+        lats.append(lat)
+        betas.append(2.2 + 0.5 * j / 15)
+    batch = su2.Batch(lats, betas)
+    d_sweep = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    poly = [torch.zeros(2, dtype=torch.float64, device="cuda:0") for _ in lats]
+    corr = [torch.zeros(lat.n[0] // 2, dtype=torch.float64, device="cuda:0") for lat in lats]
+    hist = torch.zeros((args.steps + args.warmup, 16, 2), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        su2.su2_batch_heatbath_sweep(batch, args.seed, d_sweep=d_sweep)
+        su2.su2_batch_overrelax(batch, args.or_per_hb)
+        for lat, q, c in zip(lats, poly, corr):
+            su2.su2_polyakov(lat, q, c)
+        su2.su2_sweep_advance(d_sweep)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def sweep(k):
+        graph.replay()
+        for j in range(16):
+            hist[k, j].copy_(poly[j], non_blocking=True)
+
+    for k in range(args.warmup):
+        sweep(k)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for k in range(args.steps):
+        sweep(args.warmup + k)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    vol = sum(lat.volume for lat in lats)
+    updates = 4 * vol * (1 + args.or_per_hb)
+    flags = 0
+    for lat in lats:
+        flags |= int(su2.su2_get_flags(lat).item())
+    absl = hist[args.warmup:, :, 0].abs().mean(0).cpu().tolist()
+    rec = {
+        "metric": METRIC,
+        "value": updates * args.steps / (ms * 1e-3),
+        "unit": "link updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": "finite-temperature scan: 16 SU(2) lattices cycling 32^3x4, 48^3x6, 64^3x8, "
+                        "beta 2.2..2.7, hot start, per sweep one captured graph: 1 heat-bath + "
+                        f"{args.or_per_hb} overrelaxation sweeps of all lattices + Polyakov loop and "
+                        "correlator of each",
+            "lattices": [list(lat.n) for lat in lats],
+            "betas": betas,
+            "link_updates_per_step": updates,
+        },
+        "polyakov_abs_mean_by_beta": dict(zip([round(b, 4) for b in betas], absl)),
+        "check": {"flags": flags},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the lattice update is single-GPU in this build)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "scan":
+        scan(args)
+        return
 
     import torch
     import paper_1104_5432_amd as su2
@@ -111,8 +204,15 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    lat = su2.Lattice(n, args.prec, device=dev)
-    su2.su2_init_hot(lat, args.seed)
+    tile = args.tile
+    if args.autotune:
+        from paper_1104_5432_amd import autotune
+        tile = autotune.tune(n, args.prec, device=dev)
+    lat = su2.Lattice(n, args.prec, device=dev, tile=tile)
+    if args.start == "hot":
+        su2.su2_init_hot(lat, args.seed)
+    else:
+        su2.su2_init_cold(lat)
     plaq = torch.empty((max(args.steps, 1), 7), dtype=torch.float64, device=dev)
     poly = torch.empty((max(args.steps, 1), 2), dtype=torch.float64, device=dev)
     corr = torch.empty((max(args.steps, 1), max(1, min(n[:3]) // 2)), dtype=torch.float64, device=dev)
@@ -187,12 +287,14 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"SU(2) pure gauge {'^'.join([str(n[0]), '4']) if len(set(n)) == 1 else 'x'.join(map(str, n))} "
-                        f"periodic, beta={args.beta}, hot start (Philox seed {args.seed}), "
+                        f"periodic, beta={args.beta}, {args.start} start (Philox seed {args.seed}), "
                         f"{args.prec.upper()} links, per step 1 heat-bath + {args.or_per_hb} overrelaxation "
                         f"sweeps + FP64 plaquette + Polyakov loop/correlator",
             "lattice": list(n),
             "beta": args.beta,
             "or_per_hb": args.or_per_hb,
+            "tile": tile,
+            "start": args.start,
             "link_updates_per_step": updates,
         },
         "roofline": {

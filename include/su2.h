@@ -78,6 +78,12 @@ typedef struct su2_lattice {
     int32_t n[4];        /* (Nx, Ny, Nz, Nt) */
     int32_t prec;        /* SU2_F64 or SU2_F32 */
     int32_t lattice_id;  /* 0 .. 2^27-1; enters the random-number counter */
+    int32_t tile;        /* order in which the threads of a class walk the
+                            lattice (performance only, results do not depend
+                            on it): 0 = default, W > 0 = (z,t) columns in
+                            z-strips of width W (W must divide Nz), < 0 =
+                            plain checkerboard-index order */
+    int32_t reserved;    /* set to 0 */
     void *links;         /* device, >= su2_links_bytes(n, prec) */
     void *work;          /* device, >= su2_workspace_bytes(n, prec) */
     uint64_t work_bytes; /* size of work in bytes */
@@ -135,6 +141,38 @@ int su2_plaquette(const su2_lattice_t *lat, double *d_out, void *stream);
  * correlator of eq. (3), C(r) = (1/(3 Vs)) sum_x sum_i L(x) L(x + r e_i),
  * r = 1..R.  FP64 sums, fixed reduction order. */
 int su2_polyakov(const su2_lattice_t *lat, double *d_out, double *d_corr, void *stream);
+
+/* ---- Batches: many independent lattices per launch (a temperature scan) ----
+ * A batch is count lattice descriptors of one precision, each with its own
+ * extents, beta, lattice_id (distinct ids give independent random streams;
+ * a lattice gives bit-identical links whether it is updated alone or in a
+ * batch) and tile.  su2_batch_fill writes a table into HOST memory; the
+ * caller copies it to device memory (8-byte aligned) and passes that copy as
+ * d_table together with the same descriptors.  The table holds the link and
+ * workspace pointers and betas: refill it when any of them changes. */
+
+/* Bytes of the batch table for count lattices (0 if count < 1 or > 4096). */
+uint64_t su2_batch_table_bytes(int32_t count);
+
+/* Fill host_table for lats[0..count) with betas[0..count) (host arrays).
+ * Checks every descriptor as the single-lattice calls do, one precision. */
+int su2_batch_fill(const su2_lattice_t *lats, const double *betas, int32_t count, void *host_table,
+                   uint64_t table_bytes);
+
+/* One heat-bath sweep of every lattice of the batch (the per-lattice sweep of
+ * su2_heatbath_sweep with that lattice's beta): eight launches, each updating
+ * one class (mu, parity) of all lattices.  The sweep index is *d_sweep
+ * (device, read when the launches run) if d_sweep is not NULL, else sweep;
+ * with d_sweep and su2_sweep_advance a captured graph can be replayed. */
+int su2_batch_heatbath_sweep(const su2_lattice_t *lats, int32_t count, const void *d_table, uint64_t seed,
+                             uint32_t sweep, const uint32_t *d_sweep, void *stream);
+
+/* n_sweeps overrelaxation sweeps of every lattice of the batch. */
+int su2_batch_overrelax(const su2_lattice_t *lats, int32_t count, const void *d_table, int32_t n_sweeps,
+                        void *stream);
+
+/* *d_sweep += 1 on the device (d_sweep: device, one uint32). */
+int su2_sweep_advance(uint32_t *d_sweep, void *stream);
 
 /* Copy the sticky flags word to d_flags (device, one uint32). */
 int su2_get_flags(const su2_lattice_t *lat, uint32_t *d_flags, void *stream);

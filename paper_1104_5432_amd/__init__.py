@@ -32,6 +32,8 @@ class su2_lattice_t(ctypes.Structure):
         ("n", ctypes.c_int32 * 4),
         ("prec", ctypes.c_int32),
         ("lattice_id", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("links", ctypes.c_void_p),
         ("work", ctypes.c_void_p),
         ("work_bytes", ctypes.c_uint64),
@@ -60,6 +62,12 @@ _SIGNATURES = {
     "su2_plaquette": (ctypes.c_int, [_LP, _VP, _VP]),
     "su2_polyakov": (ctypes.c_int, [_LP, _VP, _VP, _VP]),
     "su2_get_flags": (ctypes.c_int, [_LP, _VP, _VP]),
+    "su2_batch_table_bytes": (ctypes.c_uint64, [ctypes.c_int32]),
+    "su2_batch_fill": (ctypes.c_int, [_LP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _VP, ctypes.c_uint64]),
+    "su2_batch_heatbath_sweep": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, ctypes.c_uint64, ctypes.c_uint32, _VP,
+                                                _VP]),
+    "su2_batch_overrelax": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, ctypes.c_int32, _VP]),
+    "su2_sweep_advance": (ctypes.c_int, [_VP, _VP]),
     "su2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "su2_last_error": (ctypes.c_char_p, []),
 }
@@ -113,7 +121,7 @@ class Lattice:
     """Device storage for one lattice: links and workspace as uint8 tensors,
     plus the su2_lattice_t descriptor that points at them."""
 
-    def __init__(self, n, prec="f64", device="cuda", lattice_id=0):
+    def __init__(self, n, prec="f64", device="cuda", lattice_id=0, tile=0):
         self.n, cn = _dims(n)
         self.prec = _PRECS[prec]
         nb = su2_links_bytes(self.n, self.prec)
@@ -123,7 +131,7 @@ class Lattice:
         self.device = torch.device(device)
         self.links = torch.empty(nb, dtype=torch.uint8, device=self.device)
         self.work = torch.zeros(wb, dtype=torch.uint8, device=self.device)
-        self.desc = su2_lattice_t(cn, self.prec, int(lattice_id), self.links.data_ptr(),
+        self.desc = su2_lattice_t(cn, self.prec, int(lattice_id), int(tile), 0, self.links.data_ptr(),
                                   self.work.data_ptr(), wb)
 
     @property
@@ -190,6 +198,55 @@ def su2_get_flags(lat, out=None, stream=None):
         out = torch.empty(1, dtype=torch.int32, device=lat.device)
     _check(lib.su2_get_flags(lat.ref(), out.data_ptr(), _stream(stream)))
     return out
+
+
+def su2_batch_table_bytes(count):
+    return int(lib.su2_batch_table_bytes(int(count)))
+
+
+def su2_batch_fill(lattices, betas):
+    """Fill and return the host batch table (bytes) for these lattices and betas."""
+    count = len(lattices)
+    descs = (su2_lattice_t * count)(*[lat.desc for lat in lattices])
+    bvals = (ctypes.c_double * count)(*[float(b) for b in betas])
+    nbytes = su2_batch_table_bytes(count)
+    if nbytes == 0:
+        raise Su2Error(SU2_EINVAL, "count must be in [1, 4096]")
+    host = (ctypes.c_char * nbytes)()
+    _check(lib.su2_batch_fill(descs, bvals, count, host, nbytes))
+    return bytes(host), descs
+
+
+class Batch:
+    """Independent lattices of one precision updated together: the host table
+    filled by su2_batch_fill, copied to a device tensor, plus the host array
+    of descriptors the batched calls take."""
+
+    def __init__(self, lattices, betas):
+        self.lattices = list(lattices)
+        count = len(self.lattices)
+        if count != len(betas):
+            raise ValueError("one beta per lattice")
+        self.count = count
+        host, self.descs = su2_batch_fill(self.lattices, betas)
+        self.table = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(self.lattices[0].device)
+
+
+def su2_batch_heatbath_sweep(batch, seed, sweep=0, d_sweep=None, stream=None):
+    """One heat-bath sweep of every lattice; the sweep index is d_sweep[0]
+    (a device int32 tensor, read when the kernels run) if given, else sweep."""
+    _check(lib.su2_batch_heatbath_sweep(batch.descs, batch.count, batch.table.data_ptr(), int(seed), int(sweep),
+                                        d_sweep.data_ptr() if d_sweep is not None else None, _stream(stream)))
+
+
+def su2_batch_overrelax(batch, n_sweeps=1, stream=None):
+    _check(lib.su2_batch_overrelax(batch.descs, batch.count, batch.table.data_ptr(), int(n_sweeps),
+                                   _stream(stream)))
+
+
+def su2_sweep_advance(d_sweep, stream=None):
+    """d_sweep[0] += 1 on the device."""
+    _check(lib.su2_sweep_advance(d_sweep.data_ptr(), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

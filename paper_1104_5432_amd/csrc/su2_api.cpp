@@ -53,6 +53,8 @@ int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayou
         return fail(SU2_EDIMS, "extents must be even, >= 2, with volume < 2^32");
     if (lat->lattice_id < 0 || lat->lattice_id >= (1 << 27))
         return fail(SU2_EINVAL, "lattice_id must be in [0, 2^27)");
+    if (lat->tile > 0 && (lat->tile > lat->n[2] || lat->n[2] % lat->tile != 0))
+        return fail(SU2_EINVAL, "a positive tile (strip width) must divide Nz");
     if (!lat->links || !lat->work)
         return fail(SU2_EINVAL, "links and work must be non-NULL device pointers");
     if (!aligned(lat->links, 16) || !aligned(lat->work, 16))
@@ -66,6 +68,7 @@ int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayou
     out->n[3] = lat->n[3];
     out->prec = lat->prec;
     out->lattice_id = lat->lattice_id;
+    out->tile = lat->tile;
     out->volume = (uint64_t)lat->n[0] * lat->n[1] * lat->n[2] * lat->n[3];
     out->links = lat->links;
     out->work = static_cast<char *>(lat->work);
@@ -102,6 +105,37 @@ int launched()
 uint64_t round256(uint64_t b)
 {
     return (b + 255) & ~uint64_t(255);
+}
+
+constexpr int kMaxBatch = 4096;
+
+uint32_t round8(uint32_t b)
+{
+    return (b + 7u) & ~7u;
+}
+
+// Checks of a batch's descriptors; *total receives the blocks of one batched class launch.
+int check_batch(const su2_lattice_t *lats, int32_t count, uint32_t *total)
+{
+    if (!lats)
+        return fail(SU2_EINVAL, "lats must be a non-NULL host array");
+    if (count < 1 || count > kMaxBatch)
+        return fail(SU2_EINVAL, "count must be in [1, 4096]");
+    uint64_t sum = 0;
+    for (int j = 0; j < count; ++j) {
+        su2::LaunchArgs a;
+        const int rc = check_lattice(&lats[j], &a, nullptr);
+        if (rc)
+            return rc;
+        if (lats[j].prec != lats[0].prec)
+            return fail(SU2_EINVAL, "all lattices of a batch must have the same precision");
+        sum += round8(su2::class_blocks(a));
+    }
+    if (sum >= (1ull << 31))
+        return fail(SU2_EDIMS, "a batch must have fewer than 2^31 blocks per class");
+    if (total)
+        *total = (uint32_t)sum;
+    return SU2_OK;
 }
 
 } // namespace
@@ -186,7 +220,7 @@ int su2_heatbath_halfsweep(const su2_lattice_t *lat, double beta, uint64_t seed,
         rc = check_class(mu, parity);
     if (rc)
         return rc;
-    su2::launch_heatbath(a, beta, seed, sweep, mu, parity, (hipStream_t)stream);
+    su2::launch_heatbath(a, beta, seed, sweep, nullptr, mu, parity, (hipStream_t)stream);
     return launched();
 }
 
@@ -200,7 +234,7 @@ int su2_heatbath_sweep(const su2_lattice_t *lat, double beta, uint64_t seed, uin
         return rc;
     for (int mu = 0; mu < 4; ++mu)
         for (int p = 0; p < 2; ++p)
-            su2::launch_heatbath(a, beta, seed, sweep, mu, p, (hipStream_t)stream);
+            su2::launch_heatbath(a, beta, seed, sweep, nullptr, mu, p, (hipStream_t)stream);
     return launched();
 }
 
@@ -258,6 +292,83 @@ int su2_polyakov(const su2_lattice_t *lat, double *d_out, double *d_corr, void *
     if (!aligned(d_out, 8) || (d_corr && !aligned(d_corr, 8)))
         return fail(SU2_EALIGN, "d_out and d_corr must be 8-byte aligned");
     su2::launch_polyakov(a, w, d_out, d_corr, (hipStream_t)stream);
+    return launched();
+}
+
+uint64_t su2_batch_table_bytes(int32_t count)
+{
+    if (count < 1 || count > kMaxBatch)
+        return 0;
+    return (uint64_t)count * su2::batch_entry_bytes();
+}
+
+int su2_batch_fill(const su2_lattice_t *lats, const double *betas, int32_t count, void *host_table,
+                   uint64_t table_bytes)
+{
+    int rc = check_batch(lats, count, nullptr);
+    if (rc)
+        return rc;
+    if (!betas || !host_table)
+        return fail(SU2_EINVAL, "betas and host_table must be non-NULL host pointers");
+    if (table_bytes < su2_batch_table_bytes(count))
+        return fail(SU2_EWORK, "table_bytes is smaller than su2_batch_table_bytes()");
+    for (int j = 0; j < count; ++j)
+        if ((rc = check_beta(betas[j])))
+            return rc;
+    uint32_t block0 = 0;
+    for (int j = 0; j < count; ++j) {
+        su2::LaunchArgs a;
+        check_lattice(&lats[j], &a, nullptr);
+        const uint32_t nb = round8(su2::class_blocks(a));
+        su2::fill_batch_entry(a, betas[j], block0, nb, static_cast<char *>(host_table) + j * su2::batch_entry_bytes());
+        block0 += nb;
+    }
+    return SU2_OK;
+}
+
+int su2_batch_heatbath_sweep(const su2_lattice_t *lats, int32_t count, const void *d_table, uint64_t seed,
+                             uint32_t sweep, const uint32_t *d_sweep, void *stream)
+{
+    uint32_t total = 0;
+    int rc = check_batch(lats, count, &total);
+    if (rc)
+        return rc;
+    if (!d_table || !aligned(d_table, 8))
+        return fail(SU2_EINVAL, "d_table must be an 8-byte aligned device pointer");
+    if (d_sweep && !aligned(d_sweep, 4))
+        return fail(SU2_EALIGN, "d_sweep must be 4-byte aligned");
+    for (int mu = 0; mu < 4; ++mu)
+        for (int p = 0; p < 2; ++p)
+            su2::launch_heatbath_batch(d_table, count, lats[0].prec, total, mu, p, seed, sweep, d_sweep,
+                                       (hipStream_t)stream);
+    return launched();
+}
+
+int su2_batch_overrelax(const su2_lattice_t *lats, int32_t count, const void *d_table, int32_t n_sweeps,
+                        void *stream)
+{
+    uint32_t total = 0;
+    int rc = check_batch(lats, count, &total);
+    if (rc)
+        return rc;
+    if (!d_table || !aligned(d_table, 8))
+        return fail(SU2_EINVAL, "d_table must be an 8-byte aligned device pointer");
+    if (n_sweeps < 0)
+        return fail(SU2_EINVAL, "n_sweeps must be >= 0");
+    for (int s = 0; s < n_sweeps; ++s)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int p = 0; p < 2; ++p)
+                su2::launch_overrelax_batch(d_table, count, lats[0].prec, total, mu, p, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_sweep_advance(uint32_t *d_sweep, void *stream)
+{
+    if (!d_sweep)
+        return fail(SU2_EINVAL, "d_sweep must be a device pointer");
+    if (!aligned(d_sweep, 4))
+        return fail(SU2_EALIGN, "d_sweep must be 4-byte aligned");
+    su2::launch_sweep_advance(d_sweep, (hipStream_t)stream);
     return launched();
 }
 

@@ -169,21 +169,19 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
     return (__umulhi(n, f.m) + n) >> f.l;
 }
 
-// Order in which the blocks of one checkerboard class walk the lattice.
-// A block covers 256 consecutive cb indices.  In strip mode (used when a
-// (z,t) column of C = Nx*Ny/2 cb indices is a whole number S of blocks and
-// the strip width W divides Nz), columns are visited strip by strip of W
-// z-values, t-major inside a strip: the +-t neighbours of a column are then
-// W columns away in dispatch order and still in the XCD's L2, instead of a
-// whole t-slice away.  Mode 0 is plain cb order.  Every order is a bijection
-// onto the blocks, so results do not depend on it.
+// Order in which the threads of one checkerboard class walk its V/2 sites.
+// A block takes 256 consecutive indices i of the walk; hardware blocks are
+// renumbered (xcd_tile) so that each XCD takes one contiguous range of the
+// walk.  In strip mode the walk visits (z,t) columns (C = Nx*Ny/2 cb indices
+// each) strip by strip of W z-values, t-major inside a strip: the +-t halo
+// of a column is W columns behind in the walk, still in the XCD's L2,
+// instead of a whole t-slice behind.  Mode 0 walks plain cb order.  Every
+// walk is a bijection onto the class, so results do not depend on it.
 struct BlockOrder {
-    uint32_t strip;      // 0 = linear, else W
-    uint32_t cols;       // C = cb indices per (z,t) column
-    uint32_t nz;         // Nz
-    FastDiv div_s;       // by S = C / 256
-    FastDiv div_w;       // by W
-    FastDiv div_nt;      // by Nt
+    uint32_t strip;  // 0 = plain cb order, else the strip width W (divides Nz)
+    uint32_t cols;   // C
+    uint32_t nz;     // Nz
+    FastDiv div_cols, div_w, div_nt;
 };
 
 // ---------------------------------------------------------------------------
@@ -197,6 +195,18 @@ struct Geom {
     uint32_t vs;   // Nx Ny Nz
     FastDiv div_nx, div_nxh, div_ny, div_nz;
     BlockOrder ord;
+};
+
+// One lattice of a batched launch (filled on the host, read by every block).
+struct BatchEntry {
+    Geom g;
+    void *links;
+    uint32_t *flags;
+    double beta;
+    uint32_t lid16;   // 16 * lattice_id, the lattice's share of counter word c1
+    uint32_t block0;  // first block of this lattice in the batched grid (multiple of 8)
+    uint32_t nblocks; // blocks of this lattice (multiple of 8)
+    uint32_t unused;
 };
 
 struct Site {
@@ -308,20 +318,19 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks)
     return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
-// First cb index of the block handled by hardware block b of nblocks.
-__device__ __forceinline__ uint32_t block_base(uint32_t b, uint32_t nblocks, const BlockOrder &o)
+// cb index of the i-th site of the walk.
+__device__ __forceinline__ uint32_t walk_cb(uint32_t i, const BlockOrder &o)
 {
-    const uint32_t k = xcd_tile(b, nblocks);
     if (o.strip == 0)
-        return k * 256u;
-    const uint32_t j = fdiv(k, o.div_s);
-    const uint32_t sub = k - j * o.div_s.d;
+        return i;
+    const uint32_t j = fdiv(i, o.div_cols);
+    const uint32_t off = i - j * o.cols;
     const uint32_t q = fdiv(j, o.div_w);
     const uint32_t zz = j - q * o.strip;
     const uint32_t s = fdiv(q, o.div_nt);
     const uint32_t t = q - s * o.div_nt.d;
     const uint32_t z = s * o.strip + zz;
-    return sub * 256u + o.cols * (z + o.nz * t);
+    return off + o.cols * (z + o.nz * t);
 }
 
 } // namespace su2

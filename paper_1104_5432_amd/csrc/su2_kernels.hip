@@ -7,7 +7,7 @@
 #include "su2_device.hpp"
 #include "su2_launch.hpp"
 
-#include <cstdlib>
+#include <cstring>
 
 namespace su2 {
 
@@ -177,9 +177,9 @@ struct Direction<float> {
 // so a wave64 no longer idles until its slowest lane accepts.  A link's
 // attempt sequence, and so its result, does not depend on which lane runs it.
 template <class T, int MU>
-__global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, int par, double beta,
-                                                           uint32_t k0, uint32_t k1, uint32_t c1,
-                                                           uint32_t sweep, uint32_t *flags)
+__device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, int par, double beta,
+                                              uint32_t k0, uint32_t k1, uint32_t c1, uint32_t sweep,
+                                              uint32_t *flags, uint32_t b, uint32_t nblocks)
 {
     __shared__ uint32_t s_queue[kBlock];
     __shared__ uint32_t s_site[kBlock];
@@ -189,8 +189,9 @@ __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, in
     __shared__ uint32_t s_wcount[kBlock / 64];
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t cb = block_base(blockIdx.x, gridDim.x, g.ord) + tid;
-    const bool valid = cb < g.half;
+    const uint32_t i = xcd_tile(b, nblocks) * kBlock + tid;
+    const bool valid = i < g.half;
+    const uint32_t cb = valid ? walk_cb(i, g.ord) : 0u;
 
     Site s = {};
     Quat<T> Vh = {1, 0, 0, 0};
@@ -236,8 +237,8 @@ __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, in
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w)
         total += s_wcount[w];
-    for (uint32_t i = tid; i < total; i += kBlock) {
-        uint32_t w = 0, r = i;
+    for (uint32_t qi = tid; qi < total; qi += kBlock) {
+        uint32_t w = 0, r = qi;
         while (r >= s_wcount[w]) {
             r -= s_wcount[w];
             ++w;
@@ -270,11 +271,13 @@ __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, in
 // Overrelaxation for one class: U -> Vhat^+ U^+ Vhat^+ = (Vhat U Vhat)^+.
 // ---------------------------------------------------------------------------
 template <class T, int MU>
-__global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags)
+__device__ __forceinline__ void overrelax_body(const Links<T> &U, const Geom &g, int par, uint32_t *flags,
+                                               uint32_t b, uint32_t nblocks)
 {
-    const uint32_t cb = block_base(blockIdx.x, gridDim.x, g.ord) + threadIdx.x;
-    if (cb >= g.half)
+    const uint32_t i = xcd_tile(b, nblocks) * kBlock + threadIdx.x;
+    if (i >= g.half)
         return;
+    const uint32_t cb = walk_cb(i, g.ord);
     const Site s = site_of_cb(g, cb, par);
     const Quat<T> V = staple<T, MU>(U, g, s, cb, par);
     const Quat<T> u = U.ld(MU, par, cb);
@@ -290,6 +293,68 @@ __global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, i
     const Quat<T> Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
     const Quat<T> w = qmul(qmul(Vh, u), Vh);
     U.st(MU, par, cb, unitize(Quat<T>{w.w, -w.x, -w.y, -w.z}));
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: one lattice, or a batch of lattices in one launch.  A batch is a
+// device table of BatchEntry (geometry, links, beta, lattice id, flags and
+// the lattice's range of blocks, a multiple of 8 so that every lattice keeps
+// its XCD-aligned walk); a block finds its lattice by a scan of the table.
+// The heat-bath sweep index is read from device memory when `d_sweep` is
+// given, so a captured graph can be replayed sweep after sweep.
+// ---------------------------------------------------------------------------
+template <class T, int MU>
+__global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, int par, double beta,
+                                                           uint32_t k0, uint32_t k1, uint32_t c1,
+                                                           uint32_t sweep, const uint32_t *d_sweep,
+                                                           uint32_t *flags)
+{
+    const uint32_t sw = d_sweep ? *d_sweep : sweep;
+    heatbath_body<T, MU>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x);
+}
+
+template <class T, int MU>
+__global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags)
+{
+    overrelax_body<T, MU>(U, g, par, flags, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ const BatchEntry &find_entry(const BatchEntry *tab, int count)
+{
+    int j = 0;
+    while (j + 1 < count && blockIdx.x >= tab[j + 1].block0)
+        ++j;
+    return tab[j];
+}
+
+template <class T, int MU>
+__global__ __launch_bounds__(kBlock) void heatbath_batch_kernel(const BatchEntry *tab, int count, int par,
+                                                                 uint32_t k0, uint32_t k1, uint32_t sweep,
+                                                                 const uint32_t *d_sweep)
+{
+    const BatchEntry &e = find_entry(tab, count);
+    Links<T> U;
+    U.p = reinterpret_cast<decltype(U.p)>(e.links);
+    U.half = e.g.half;
+    const uint32_t sw = d_sweep ? *d_sweep : sweep;
+    const uint32_t c1 = (uint32_t)MU + 4u * 1u + e.lid16;
+    heatbath_body<T, MU>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, blockIdx.x - e.block0, e.nblocks);
+}
+
+template <class T, int MU>
+__global__ __launch_bounds__(kBlock) void overrelax_batch_kernel(const BatchEntry *tab, int count, int par)
+{
+    const BatchEntry &e = find_entry(tab, count);
+    Links<T> U;
+    U.p = reinterpret_cast<decltype(U.p)>(e.links);
+    U.half = e.g.half;
+    overrelax_body<T, MU>(U, e.g, par, e.flags, blockIdx.x - e.block0, e.nblocks);
+}
+
+__global__ void sweep_advance_kernel(uint32_t *d_sweep)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        *d_sweep += 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -374,8 +439,9 @@ __global__ __launch_bounds__(kBlock) void plaquette_kernel(Links<T> U, Geom g, d
 {
     __shared__ double lds[kBlock / 64][6];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    const uint32_t cb = block_base(blockIdx.x, gridDim.x, g.ord) + threadIdx.x;
-    if (cb < g.half) {
+    const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i < g.half) {
+        const uint32_t cb = walk_cb(i, g.ord);
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
             const int opp = par ^ 1;
@@ -493,33 +559,34 @@ __global__ void copy_flags_kernel(const uint32_t *flags, uint32_t *dst)
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-// Strip width of the block order: SU2_STRIP_WIDTH if set (0 = plain cb
-// order), else Nz/8 rounded down to a divisor of Nz, so that the eight XCDs
-// each take one strip range.  Strips need whole blocks per (z,t) column.
-static BlockOrder make_block_order(const int32_t n[4])
+int default_strip(const int32_t n[4])
 {
-    BlockOrder o = {};
-    const uint32_t cols = (uint32_t)n[0] / 2u * (uint32_t)n[1];
     const uint32_t nz = (uint32_t)n[2];
-    o.cols = cols;
-    o.nz = nz;
-    if (cols % kBlock != 0)
-        return o;
     uint32_t w = nz / 8u > 0 ? nz / 8u : 1u;
-    if (const char *env = getenv("SU2_STRIP_WIDTH"))
-        w = (uint32_t)atoi(env);
-    if (w == 0)
-        return o;
     while (nz % w)
         --w;
-    o.strip = w;
-    o.div_s = make_fastdiv(cols / kBlock);
-    o.div_w = make_fastdiv(w);
+    return (int)w;
+}
+
+// Walk of a class: tile > 0 is the strip width (it divides Nz; the caller
+// checked), tile == 0 the default (Nz/8 rounded down to a divisor of Nz, so
+// that each of the 8 XCDs takes one strip), tile < 0 plain cb order.
+static BlockOrder make_block_order(const int32_t n[4], int tile)
+{
+    BlockOrder o = {};
+    o.cols = (uint32_t)n[0] / 2u * (uint32_t)n[1];
+    o.nz = (uint32_t)n[2];
+    const int w = tile == 0 ? default_strip(n) : tile;
+    if (w <= 0)
+        return o;
+    o.strip = (uint32_t)w;
+    o.div_cols = make_fastdiv(o.cols);
+    o.div_w = make_fastdiv(o.strip);
     o.div_nt = make_fastdiv((uint32_t)n[3]);
     return o;
 }
 
-static Geom make_geom(const int32_t n[4])
+static Geom make_geom(const int32_t n[4], int tile)
 {
     Geom g;
     for (int d = 0; d < 4; ++d)
@@ -532,7 +599,7 @@ static Geom make_geom(const int32_t n[4])
     g.div_nxh = make_fastdiv(g.nxh);
     g.div_ny = make_fastdiv((uint32_t)n[1]);
     g.div_nz = make_fastdiv((uint32_t)n[2]);
-    g.ord = make_block_order(n);
+    g.ord = make_block_order(n, tile);
     return g;
 }
 
@@ -550,19 +617,42 @@ static uint32_t blocks_for(uint64_t n)
     return (uint32_t)((n + kBlock - 1) / kBlock);
 }
 
+uint32_t class_blocks(const LaunchArgs &a)
+{
+    return blocks_for(a.volume / 2);
+}
+
+uint64_t batch_entry_bytes()
+{
+    return sizeof(BatchEntry);
+}
+
+void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_t nblocks, void *dst)
+{
+    BatchEntry e = {};
+    e.g = make_geom(a.n, a.tile);
+    e.links = a.links;
+    e.flags = a.flags;
+    e.beta = beta;
+    e.lid16 = 16u * (uint32_t)a.lattice_id;
+    e.block0 = block0;
+    e.nblocks = nblocks;
+    std::memcpy(dst, &e, sizeof e);
+}
+
 template <class T>
 static void launch_hb(const LaunchArgs &a, const Geom &g, int mu, int par, double beta, uint64_t seed,
-                      uint32_t sweep, hipStream_t st)
+                      uint32_t sweep, const uint32_t *d_sweep, hipStream_t st)
 {
     const Links<T> U = links_of<T>(a);
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = (uint32_t)mu + 4u * 1u + 16u * (uint32_t)a.lattice_id;
     const dim3 grid(blocks_for(g.half)), block(kBlock);
     switch (mu) {
-    case 0: heatbath_kernel<T, 0><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, a.flags); break;
-    case 1: heatbath_kernel<T, 1><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, a.flags); break;
-    case 2: heatbath_kernel<T, 2><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, a.flags); break;
-    default: heatbath_kernel<T, 3><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, a.flags); break;
+    case 0: heatbath_kernel<T, 0><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, a.flags); break;
+    case 1: heatbath_kernel<T, 1><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, a.flags); break;
+    case 2: heatbath_kernel<T, 2><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, a.flags); break;
+    default: heatbath_kernel<T, 3><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, a.flags); break;
     }
 }
 
@@ -581,7 +671,7 @@ static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, hipSt
 
 void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st)
 {
-    const Geom g = make_geom(a.n);
+    const Geom g = make_geom(a.n, a.tile);
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const uint32_t lid16 = 16u * (uint32_t)a.lattice_id;
     const dim3 grid(blocks_for(g.half)), block(kBlock);
@@ -591,28 +681,79 @@ void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st)
         init_kernel<double><<<grid, block, 0, st>>>(links_of<double>(a), g, hot, k0, k1, lid16, a.flags);
 }
 
-void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, int mu, int par,
-                     hipStream_t st)
+void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, const uint32_t *d_sweep,
+                     int mu, int par, hipStream_t st)
 {
-    const Geom g = make_geom(a.n);
+    const Geom g = make_geom(a.n, a.tile);
     if (a.prec == kF32)
-        launch_hb<float>(a, g, mu, par, beta, seed, sweep, st);
+        launch_hb<float>(a, g, mu, par, beta, seed, sweep, d_sweep, st);
     else
-        launch_hb<double>(a, g, mu, par, beta, seed, sweep, st);
+        launch_hb<double>(a, g, mu, par, beta, seed, sweep, d_sweep, st);
 }
 
 void launch_overrelax(const LaunchArgs &a, int mu, int par, hipStream_t st)
 {
-    const Geom g = make_geom(a.n);
+    const Geom g = make_geom(a.n, a.tile);
     if (a.prec == kF32)
         launch_or<float>(a, g, mu, par, st);
     else
         launch_or<double>(a, g, mu, par, st);
 }
 
+template <class T>
+static void launch_hb_batch(const BatchEntry *tab, int count, uint32_t total, int mu, int par, uint64_t seed,
+                            uint32_t sweep, const uint32_t *d_sweep, hipStream_t st)
+{
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    const dim3 grid(total), block(kBlock);
+    switch (mu) {
+    case 0: heatbath_batch_kernel<T, 0><<<grid, block, 0, st>>>(tab, count, par, k0, k1, sweep, d_sweep); break;
+    case 1: heatbath_batch_kernel<T, 1><<<grid, block, 0, st>>>(tab, count, par, k0, k1, sweep, d_sweep); break;
+    case 2: heatbath_batch_kernel<T, 2><<<grid, block, 0, st>>>(tab, count, par, k0, k1, sweep, d_sweep); break;
+    default: heatbath_batch_kernel<T, 3><<<grid, block, 0, st>>>(tab, count, par, k0, k1, sweep, d_sweep); break;
+    }
+}
+
+template <class T>
+static void launch_or_batch(const BatchEntry *tab, int count, uint32_t total, int mu, int par, hipStream_t st)
+{
+    const dim3 grid(total), block(kBlock);
+    switch (mu) {
+    case 0: overrelax_batch_kernel<T, 0><<<grid, block, 0, st>>>(tab, count, par); break;
+    case 1: overrelax_batch_kernel<T, 1><<<grid, block, 0, st>>>(tab, count, par); break;
+    case 2: overrelax_batch_kernel<T, 2><<<grid, block, 0, st>>>(tab, count, par); break;
+    default: overrelax_batch_kernel<T, 3><<<grid, block, 0, st>>>(tab, count, par); break;
+    }
+}
+
+void launch_heatbath_batch(const void *d_table, int count, int prec, uint32_t total_blocks, int mu, int par,
+                           uint64_t seed, uint32_t sweep, const uint32_t *d_sweep, hipStream_t st)
+{
+    const BatchEntry *tab = static_cast<const BatchEntry *>(d_table);
+    if (prec == kF32)
+        launch_hb_batch<float>(tab, count, total_blocks, mu, par, seed, sweep, d_sweep, st);
+    else
+        launch_hb_batch<double>(tab, count, total_blocks, mu, par, seed, sweep, d_sweep, st);
+}
+
+void launch_overrelax_batch(const void *d_table, int count, int prec, uint32_t total_blocks, int mu, int par,
+                            hipStream_t st)
+{
+    const BatchEntry *tab = static_cast<const BatchEntry *>(d_table);
+    if (prec == kF32)
+        launch_or_batch<float>(tab, count, total_blocks, mu, par, st);
+    else
+        launch_or_batch<double>(tab, count, total_blocks, mu, par, st);
+}
+
+void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st)
+{
+    sweep_advance_kernel<<<1, 64, 0, st>>>(d_sweep);
+}
+
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
 {
-    const Geom g = make_geom(a.n);
+    const Geom g = make_geom(a.n, a.tile);
     double *partials = reinterpret_cast<double *>(a.work + w.off_plaq);
     if (a.prec == kF32)
         plaquette_kernel<float><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
@@ -624,7 +765,7 @@ void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, h
 
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st)
 {
-    const Geom g = make_geom(a.n);
+    const Geom g = make_geom(a.n, a.tile);
     double *Lf = reinterpret_cast<double *>(a.work + w.off_lfield);
     double *pp = reinterpret_cast<double *>(a.work + w.off_poly);
     if (a.prec == kF32)

@@ -22,6 +22,7 @@ struct LaunchArgs {
     int32_t n[4];
     int prec;
     int lattice_id;
+    int tile;
     uint64_t volume;
     void *links;
     char *work;
@@ -30,9 +31,19 @@ struct LaunchArgs {
 
 WorkLayout work_layout(const int32_t n[4]);
 
+int default_strip(const int32_t n[4]);
+uint32_t class_blocks(const LaunchArgs &a);
+uint64_t batch_entry_bytes();
+void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_t nblocks, void *dst);
+
 void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st);
-void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, int mu, int par,
-                     hipStream_t st);
+void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, const uint32_t *d_sweep,
+                     int mu, int par, hipStream_t st);
+void launch_heatbath_batch(const void *d_table, int count, int prec, uint32_t total_blocks, int mu, int par,
+                           uint64_t seed, uint32_t sweep, const uint32_t *d_sweep, hipStream_t st);
+void launch_overrelax_batch(const void *d_table, int count, int prec, uint32_t total_blocks, int mu, int par,
+                            hipStream_t st);
+void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st);
 void launch_overrelax(const LaunchArgs &a, int mu, int par, hipStream_t st);
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st);

@@ -51,10 +51,10 @@ def test_sizes(su2):
     assert su2.su2_links_bytes((256, 256, 256, 254), "f32") > 0
 
 
-def _desc(su2, n=(8, 8, 8, 8), prec=0, lid=0, links=0x10000, work=0x20000, wb=None):
+def _desc(su2, n=(8, 8, 8, 8), prec=0, lid=0, links=0x10000, work=0x20000, wb=None, tile=0):
     if wb is None:
         wb = su2.su2_workspace_bytes(n, 0) if all(v >= 2 and v % 2 == 0 for v in n) else 1 << 20
-    return su2.su2_lattice_t((ctypes.c_int32 * 4)(*n), prec, lid, links, work, wb)
+    return su2.su2_lattice_t((ctypes.c_int32 * 4)(*n), prec, lid, tile, 0, links, work, wb)
 
 
 def test_argument_checks_reject_before_any_hip_call(su2):
@@ -98,6 +98,32 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     assert L.su2_polyakov(ok, 0x30000, 0x30003, s) == su2.SU2_EALIGN
     assert L.su2_get_flags(ok, None, s) == su2.SU2_EINVAL
     assert L.su2_get_flags(ok, 0x30002, s) == su2.SU2_EALIGN
+    # tile: a positive strip width must divide Nz
+    assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 12, 8), tile=5)), s) == su2.SU2_EINVAL
+    assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 12, 8), tile=24)), s) == su2.SU2_EINVAL
+    # batches
+    d0, d1 = _desc(su2), _desc(su2, n=(4, 4, 4, 6), lid=1)
+    arr = (su2.su2_lattice_t * 2)(d0, d1)
+    betas = (ctypes.c_double * 2)(2.3, 2.4)
+    nb = L.su2_batch_table_bytes(2)
+    assert nb > 0 and L.su2_batch_table_bytes(0) == 0 and L.su2_batch_table_bytes(4097) == 0
+    host = (ctypes.c_char * nb)()
+    assert L.su2_batch_fill(arr, betas, 2, host, nb) == su2.SU2_OK      # host-only call
+    assert L.su2_batch_fill(arr, betas, 2, host, nb - 1) == su2.SU2_EWORK
+    assert L.su2_batch_fill(arr, betas, 0, host, nb) == su2.SU2_EINVAL
+    assert L.su2_batch_fill(None, betas, 2, host, nb) == su2.SU2_EINVAL
+    bad = (ctypes.c_double * 2)(2.3, float("nan"))
+    assert L.su2_batch_fill(arr, bad, 2, host, nb) == su2.SU2_EINVAL
+    mixed = (su2.su2_lattice_t * 2)(d0, _desc(su2, prec=1))
+    assert L.su2_batch_fill(mixed, betas, 2, host, nb) == su2.SU2_EINVAL
+    oddb = (su2.su2_lattice_t * 2)(d0, _desc(su2, n=(4, 5, 4, 6)))
+    assert L.su2_batch_fill(oddb, betas, 2, host, nb) == su2.SU2_EDIMS
+    assert L.su2_batch_heatbath_sweep(arr, 2, None, 1, 0, None, s) == su2.SU2_EINVAL
+    assert L.su2_batch_heatbath_sweep(arr, 2, 0x40004, 1, 0, None, s) == su2.SU2_EINVAL
+    assert L.su2_batch_heatbath_sweep(arr, 2, 0x40000, 1, 0, 0x50002, s) == su2.SU2_EALIGN
+    assert L.su2_batch_overrelax(arr, 2, 0x40000, -1, s) == su2.SU2_EINVAL
+    assert L.su2_sweep_advance(None, s) == su2.SU2_EINVAL
+    assert L.su2_sweep_advance(0x50001, s) == su2.SU2_EALIGN
     # messages
     assert L.su2_strerror(su2.SU2_EWORK) == b"workspace too small"
     assert b"beta" in L.su2_last_error() or len(L.su2_last_error()) > 0

@@ -29,9 +29,8 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-# (16, 32, 8, 4) and (32, 16, 8, 2) have whole 256-site blocks per (z,t) column and
-# so run in the strip block order; the others run in plain cb order with a
-# ragged last block.
+# Every shape runs the default strip walk (width Nz/8 rounded down to a
+# divisor of Nz); (6, 4, 10, 8) and (10, 6, 4, 6) also have a ragged last block.
 SHAPES = [(8, 8, 8, 8), (6, 4, 10, 8), (2, 2, 2, 2), (4, 6, 2, 12), (10, 6, 4, 6), (16, 32, 8, 4),
           (32, 16, 8, 2)]
 
@@ -338,14 +337,13 @@ def test_full_size_64(su2, prec):
 # determinism, resume, failure flags
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_block_order_does_not_change_results(su2, prec, monkeypatch):
-    # links of one class are independent, so every block order must give
+def test_block_order_does_not_change_results(su2, prec):
+    # links of one class are independent, so every walk order must give
     # bit-identical links; plaquette sums differ only in summation order
     n = (32, 16, 8, 4)
     links, plaqs = [], []
-    for w in ("0", "1", "2", "4", "8"):
-        monkeypatch.setenv("SU2_STRIP_WIDTH", w)
-        lat = _lat(su2, n, prec)
+    for w in (-1, 0, 1, 2, 4, 8):
+        lat = su2.Lattice(n, prec, device="cuda", tile=w)
         su2.su2_init_hot(lat, 5)
         su2.su2_heatbath_sweep(lat, 2.3, 5, 0)
         su2.su2_overrelax(lat, 2)
@@ -436,3 +434,55 @@ def test_fp32_ensemble_matches_fp64(su2, beta, n):
         z = (m32 - m64) / np.hypot(e64, e32)
         print(f"{name}: f64 {m64:.6f}({e64:.6f}) f32 {m32:.6f}({e32:.6f}) z = {z:+.2f}", flush=True)
         assert abs(z) <= 3.0
+
+
+# ---------------------------------------------------------------------------
+# the largest single lattice: 96^4 FP32 (5.4 GB of links, > 4 GiB offsets)
+# ---------------------------------------------------------------------------
+def test_max_size_96_cold_start(su2):
+    n, beta, seed = (96, 96, 96, 96), 2.5, 1234
+    print(f"max-size parity {n} f32 cold start", flush=True)
+    lat = _lat(su2, n, "f32")
+    su2.su2_init_cold(lat)
+    ref = oracle.init_cold(n)
+    # a heat-bath class that wraps in t and reads the last planes of the
+    # buffer (offsets beyond 4 GiB), then an overrelaxation class
+    oracle.heatbath_halfsweep(n, ref, beta, seed, 0, 3, 1)
+    su2.su2_heatbath_halfsweep(lat, beta, seed, 0, 3, 1)
+    oracle.overrelax_halfsweep(n, ref, 0, 0)
+    su2.su2_overrelax_halfsweep(lat, 0, 0)
+    plaq = su2.su2_plaquette(lat)
+    poly, corr = su2.su2_polyakov(lat)
+    _sync()
+    got = su2.to_canonical(lat).numpy()
+    d = np.max(np.abs(got - ref), axis=-1)
+    del ref
+    # FP32 links against FP64: rounding, plus rare accept/reject flips of
+    # 23-bit against 52-bit uniforms
+    assert np.mean(d > 5e-5) <= 1e-4 and np.median(d) < 1e-6, (np.mean(d > 5e-5), np.median(d))
+    del d
+    p, planes = oracle.plaquette(n, got)
+    lm, la = oracle.polyakov(n, got)
+    g = plaq.cpu().numpy()
+    assert abs(g[0] - p) <= 1e-6 and _maxdiff(g[1:], planes) <= 1e-6
+    g = poly.cpu().numpy()
+    assert abs(g[0] - lm) <= 1e-6 and abs(g[1] - la) <= 1e-6
+    assert _flags(su2, lat) == 0
+
+
+def test_autotuner_picks_a_valid_walk(su2, tmp_path):
+    from paper_1104_5432_amd import autotune
+    n = (16, 16, 16, 8)
+    cache = str(tmp_path / "tiles.json")
+    tile = autotune.tune(n, "f32", cache=cache, reps=2)
+    assert tile in autotune.candidates(n)
+    assert autotune.tune(n, "f32", cache=cache) == tile          # cached
+    # the tuned walk changes no result
+    a = su2.Lattice(n, "f32", device="cuda", tile=tile)
+    b = su2.Lattice(n, "f32", device="cuda", tile=-1)
+    for lat in (a, b):
+        su2.su2_init_hot(lat, 3)
+        su2.su2_heatbath_sweep(lat, 2.3, 3, 0)
+        su2.su2_overrelax(lat, 1)
+    _sync()
+    assert torch.equal(a.links, b.links)
