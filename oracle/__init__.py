@@ -53,6 +53,15 @@ def lib():
             "or_polyakov_corr": (i32, [i4, dp, dp]),
             "or_gauge_transform": (None, [i4, dp, u64, u32]),
             "or_num_threads": (i32, []),
+            "or_bessel_ive": (dbl, [i32, dbl]),
+            "or_log_z": (dbl, [dbl]),
+            "or_bessel_ratio": (dbl, [dbl]),
+            "or_block_colour": (i32, [i32, i32, i32]),
+            "or_block_piece": (None, [i4, dp, i64, i32, dp]),
+            "or_block_log_marginal": (dbl, [i4, dp, i64, dbl, dp]),
+            "or_block_proposal": (None, [i4, dp, i64, dbl, dp, dp]),
+            "or_block_move": (u32, [i4, dp, dbl, u64, u32, i32, i32, dp, u32, ctypes.POINTER(ctypes.c_int64)]),
+            "or_block_sweep": (u32, [i4, dp, dbl, u64, u32, dp, u32, ctypes.POINTER(ctypes.c_int64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -202,3 +211,71 @@ def polyakov_corr(n, U):
 def gauge_transform(n, U, seed, lattice_id=0):
     _check_links(n, U)
     lib().or_gauge_transform(_dims(n), _dp(U), seed, lattice_id)
+
+
+# ---------------------------------------------------------------------------
+# learned block proposal (reference)
+# ---------------------------------------------------------------------------
+def bessel_ive(order, x):
+    return lib().or_bessel_ive(order, x)
+
+
+def log_z(a):
+    """log Z(a) = log(2 I1(a)/a): normalisation of exp(a w0) over Haar measure."""
+    return lib().or_log_z(a)
+
+
+def bessel_ratio(a):
+    return lib().or_bessel_ratio(a)
+
+
+def block_colour(x, y, z):
+    return lib().or_block_colour(x, y, z)
+
+
+def block_piece(n, U, e, direction):
+    _check_links(n, U)
+    S = np.empty(4)
+    lib().or_block_piece(_dims(n), _dp(U), e, direction, _dp(S))
+    return S
+
+
+def block_log_marginal(n, U, e, beta, T):
+    _check_links(n, U)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    return lib().or_block_log_marginal(_dims(n), _dp(U), e, beta, _dp(T))
+
+
+def block_proposal(n, U, e, beta, y6):
+    _check_links(n, U)
+    y6 = np.ascontiguousarray(y6, dtype=np.float64)
+    M = np.empty(4)
+    lib().or_block_proposal(_dims(n), _dp(U), e, beta, _dp(y6), _dp(M))
+    return M
+
+
+def _y_array(n, y):
+    nx, ny, nz, nt = n
+    if y is None:
+        y = np.zeros((nt, nz, ny, nx, 6))
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    assert y.shape == (nt, nz, ny, nx, 6)
+    return y
+
+
+def block_move(n, U, beta, seed, step, parity, colour, y=None, lattice_id=0):
+    """One class of block moves; y[t, z, y, x, d] network outputs. Returns (flags, accepted)."""
+    _check_links(n, U)
+    y = _y_array(n, y)
+    acc = ctypes.c_int64(0)
+    f = lib().or_block_move(_dims(n), _dp(U), beta, seed, step, parity, colour, _dp(y), lattice_id,
+                            ctypes.byref(acc))
+    return f, acc.value
+
+
+def block_sweep(n, U, beta, seed, step, y=None, lattice_id=0):
+    _check_links(n, U)
+    y = _y_array(n, y)
+    acc = ctypes.c_int64(0)
+    f = lib().or_block_sweep(_dims(n), _dp(U), beta, seed, step, _dp(y), lattice_id, ctypes.byref(acc))
+    return f, acc.value

@@ -521,3 +521,302 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Learned block proposal (test reference).  A move updates the temporal    */
+/* link T(e) of one spatial site e of time slice tau with the temporal      */
+/* links of its six spatial neighbours o integrated out:                     */
+/*   the marginal of T(e) is prod_o Z(beta |V_o(T(e))|), Z(a) = 2 I1(a)/a,   */
+/* because each of the six plaquettes holding T(e) holds exactly one T(o).  */
+/* T(e) is proposed from q(T) ~ exp((1/2) Tr(T M)), M = sum_o c_o S_o, and  */
+/* accepted with the Metropolis-Hastings ratio of the marginal; then every  */
+/* T(o) is redrawn by heat bath given the new T(e).  S_o is the staple of   */
+/* T(o) without the term through e, carried to e: with that term written    */
+/* X T(e)^+ Y,  S_o = X^+ V_o^rest Y^+, so that                               */
+/*   |V_o(T)|^2 = |S_o|^2 + 1 + 2 (1/2)Tr(T S_o).                           */
+/* c_o = beta r(a0)/sqrt(|S_o|^2+1) exp(y_o), a0 = beta sqrt(|S_o|^2+1),     */
+/* r = I2/I1 (the slope of log Z), y_o supplied by the caller (the network). */
+/* ======================================================================== */
+
+/* e^{-x} I_n(x).  For x >= 1: (1/2pi) int_0^{2pi} exp(x (cos t - 1))       */
+/* cos(n t) dt by the trapezoidal rule, which converges geometrically for   */
+/* this periodic analytic integrand (256 points: below 1e-15 relative for   */
+/* x <= 200).  For x < 1, where I_2 is small against the integrand and the  */
+/* rule would lose relative accuracy: the power series                      */
+/* sum_k (x/2)^(2k+n) / (k! (k+n)!).                                        */
+double or_bessel_ive(int n, double x)
+{
+    if (x < 1.0) {
+        double term = 1.0;
+        for (int j = 1; j <= n; ++j)
+            term *= 0.5 * x / j;
+        double sum = 0.0;
+        for (int k = 0; k < 30; ++k) {
+            sum += term;
+            term *= 0.25 * x * x / ((k + 1.0) * (k + 1.0 + n));
+        }
+        return sum * exp(-x);
+    }
+    const int K = 256;
+    long double s = 0.0L;
+    for (int j = 0; j < K; ++j) {
+        double t = 2.0 * OR_PI * j / K;
+        s += (long double)(exp(x * (cos(t) - 1.0)) * cos(n * t));
+    }
+    return (double)(s / K);
+}
+
+/* log Z(a) = log(2 I1(a)/a); Z(0) = 1. */
+double or_log_z(double a)
+{
+    if (a < 1e-300)
+        return 0.0;
+    return log(2.0 * or_bessel_ive(1, a) / a) + a;
+}
+
+double or_bessel_ratio(double a)
+{
+    if (a < 1e-300)
+        return 0.0;
+    return or_bessel_ive(2, a) / or_bessel_ive(1, a);
+}
+
+static double qnorm(const double a[4])
+{
+    return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+}
+
+/* (1/2) Tr(A B) = scalar part of the product. */
+static double half_tr(const double a[4], const double b[4])
+{
+    double p[4];
+    or_qmul(a, b, p);
+    return p[0];
+}
+
+/* Neighbour o = e + s e_i (s = -1, +1) of spatial direction i, and the     */
+/* pieces of the term of V_o through e: X, Y with term = X T(e)^+ Y.        */
+static void block_neighbour(const int n[4], const double *U, int64_t e, int dir, int64_t *o,
+                            double X[4], double Y[4])
+{
+    int i = dir / 2, s = (dir % 2) ? +1 : -1;
+    *o = or_neighbor(n, e, i, s);
+    if (s < 0) {
+        /* e = o + i: upper term U_i(o+t) T(o+i)^+ U_i(o)^+ */
+        int64_t ot = or_neighbor(n, *o, 3, +1);
+        memcpy(X, link(U, ot, i), 4 * sizeof(double));
+        or_qdag(link(U, *o, i), Y);
+    } else {
+        /* e = o - i: lower term U_i(o+t-i)^+ T(o-i)^+ U_i(o-i) = U_i(e+t)^+ T(e)^+ U_i(e) */
+        int64_t et = or_neighbor(n, e, 3, +1);
+        or_qdag(link(U, et, i), X);
+        memcpy(Y, link(U, e, i), 4 * sizeof(double));
+    }
+}
+
+/* S_o for direction dir (0..5 = -x,+x,-y,+y,-z,+z) of block centre e. */
+void or_block_piece(const int n[4], const double *U, int64_t e, int dir, double S[4])
+{
+    int64_t o;
+    double X[4], Y[4], V[4], t1[4], t2[4], Td[4];
+    block_neighbour(n, U, e, dir, &o, X, Y);
+    or_staple(n, U, o, 3, V);
+    /* remove the term through e */
+    or_qdag(link(U, e, 3), Td);
+    or_qmul(X, Td, t1);
+    or_qmul(t1, Y, t2);
+    for (int k = 0; k < 4; ++k)
+        V[k] -= t2[k];
+    /* S = X^+ V Y^+ */
+    double Xd[4], Yd[4];
+    or_qdag(X, Xd);
+    or_qdag(Y, Yd);
+    or_qmul(Xd, V, t1);
+    or_qmul(t1, Yd, S);
+}
+
+/* Marginal log density of T(e) = T (up to a constant) given the pieces. */
+static double block_log_marginal(double beta, const double S[6][4], const double T[4])
+{
+    double lp = 0.0;
+    for (int d = 0; d < 6; ++d) {
+        double s2 = S[d][0] * S[d][0] + S[d][1] * S[d][1] + S[d][2] * S[d][2] + S[d][3] * S[d][3];
+        double v2 = s2 + 1.0 + 2.0 * half_tr(T, S[d]);
+        lp += or_log_z(beta * sqrt(v2 > 0.0 ? v2 : 0.0));
+    }
+    return lp;
+}
+
+double or_block_log_marginal(const int n[4], const double *U, int64_t e, double beta, const double T[4])
+{
+    double S[6][4];
+    for (int d = 0; d < 6; ++d)
+        or_block_piece(n, U, e, d, S[d]);
+    return block_log_marginal(beta, S, T);
+}
+
+/* Effective staple M of the proposal at e for network outputs y[6]. */
+void or_block_proposal(const int n[4], const double *U, int64_t e, double beta, const double y[6],
+                       double M[4])
+{
+    M[0] = M[1] = M[2] = M[3] = 0.0;
+    for (int d = 0; d < 6; ++d) {
+        double S[4];
+        or_block_piece(n, U, e, d, S);
+        double s = qnorm(S);
+        double a0 = beta * sqrt(s * s + 1.0);
+        double c = beta * or_bessel_ratio(a0) / sqrt(s * s + 1.0) * exp(y[d]);
+        for (int k = 0; k < 4; ++k)
+            M[k] += c * S[k];
+    }
+}
+
+/* Draw W with density ~ exp(alpha w0) dHaar (the heat-bath law) from the   */
+/* counter stream (c0, c1, c2, 4 attempt + draw); returns 0 on success.     */
+static uint32_t sample_w(double alpha, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, double W[4])
+{
+    double x0 = 0.0, xlen = 0.0;
+    int ok = 0;
+    for (uint32_t a = 0; a < OR_MAX_ATTEMPTS && !ok; ++a) {
+        if (alpha >= 2.0) {
+            double u1, u2, u3, u4;
+            draw2(seed, c0, c1, c2, 4u * a + 0u, &u1, &u2);
+            draw2(seed, c0, c1, c2, 4u * a + 1u, &u3, &u4);
+            double c = cos(2.0 * OR_PI * u2);
+            double lam2 = -(log(u1) + c * c * log(u3)) / (2.0 * alpha);
+            if (lam2 <= 1.0 && u4 * u4 <= 1.0 - lam2) {
+                x0 = 1.0 - 2.0 * lam2;
+                xlen = 2.0 * sqrt(lam2 * (1.0 - lam2));
+                ok = 1;
+            }
+        } else {
+            double u1, u2, t;
+            draw2(seed, c0, c1, c2, 4u * a + 0u, &u1, &u2);
+            if (alpha < 1e-8) {
+                t = 2.0 * u1 - 1.0;
+            } else {
+                double ex = exp(-2.0 * alpha);
+                t = 1.0 + log(ex + u1 * (1.0 - ex)) / alpha;
+            }
+            if (u2 * u2 <= 1.0 - t * t) {
+                x0 = t;
+                double s = 1.0 - t * t;
+                xlen = sqrt(s > 0.0 ? s : 0.0);
+                ok = 1;
+            }
+        }
+    }
+    if (!ok)
+        return OR_FLAG_CAP;
+    double u5, u6;
+    draw2(seed, c0, c1, c2, 2u, &u5, &u6);
+    double cth = 2.0 * u5 - 1.0;
+    double s = 1.0 - cth * cth;
+    double sth = sqrt(s > 0.0 ? s : 0.0);
+    double phi = 2.0 * OR_PI * u6;
+    W[0] = x0;
+    W[1] = xlen * sth * cos(phi);
+    W[2] = xlen * sth * sin(phi);
+    W[3] = xlen * cth;
+    return 0;
+}
+
+/* Draw U ~ exp((1/2)Tr(U M)) dHaar: W from the law at alpha = |M|, U = W Mhat^+. */
+static uint32_t sample_vmf(const double M[4], uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                           double out[4])
+{
+    double k = qnorm(M);
+    double Mh[4] = {1.0, 0.0, 0.0, 0.0};
+    if (k > 0.0)
+        for (int j = 0; j < 4; ++j)
+            Mh[j] = M[j] / k;
+    double W[4], Md[4];
+    uint32_t f = sample_w(k, seed, c0, c1, c2, W);
+    if (f)
+        return f;
+    or_qdag(Mh, Md);
+    or_qmul(W, Md, out);
+    return 0;
+}
+
+/* Colour of a spatial site for the block classes: (x + 2y + 3z) mod 8.    */
+/* Two sites of one parity and one colour are at L1 distance >= 4, so their */
+/* blocks (centre and six neighbours) neither overlap nor read each other.  */
+int or_block_colour(int x, int y, int z)
+{
+    return (x + 2 * y + 3 * z) % 8;
+}
+
+/* All blocks of centre parity p and colour k, every time slice: the move   */
+/* described above.  y holds 6 network outputs per (slice, spatial site),   */
+/* index (t * Vs + s) * 6 + d.  Counters: (site, 3 + 4*2 + 16*lattice_id,   */
+/* 16*step + 8*p + k, 4*attempt + draw): proposal attempts draws 0,1, its   */
+/* direction draw 2, the accept uniform draw 3 (attempt 0); each refreshed   */
+/* neighbour uses its own site index with draws 0,1,2.  accepted[0] counts   */
+/* accepted moves.  Returns flag bits.                                       */
+uint32_t or_block_move(const int n[4], double *U, double beta, uint64_t seed, uint32_t step, int p, int k,
+                       const double *y, uint32_t lattice_id, int64_t *accepted)
+{
+    int64_t vs = (int64_t)n[0] * n[1] * n[2];
+    uint32_t c1 = (uint32_t)(3 + 4 * 2 + 16 * lattice_id);
+    uint32_t c2 = 16u * step + 8u * (uint32_t)p + (uint32_t)k;
+    uint32_t flags = 0;
+    int64_t acc = 0;
+#pragma omp parallel for schedule(static) reduction(| : flags) reduction(+ : acc)
+    for (int64_t i = 0; i < or_volume(n); ++i) {
+        int c[4];
+        coords(n, i, c);
+        if (((c[0] + c[1] + c[2]) & 1) != p || or_block_colour(c[0], c[1], c[2]) != k)
+            continue;
+        double S[6][4], M[4] = {0, 0, 0, 0};
+        for (int d = 0; d < 6; ++d) {
+            or_block_piece(n, U, i, d, S[d]);
+            double s = qnorm(S[d]);
+            double a0 = beta * sqrt(s * s + 1.0);
+            double cf = beta * or_bessel_ratio(a0) / sqrt(s * s + 1.0) * exp(y[(c[3] * vs + i % vs) * 6 + d]);
+            for (int j = 0; j < 4; ++j)
+                M[j] += cf * S[d][j];
+        }
+        double *T = U + (i * 4 + 3) * 4;
+        double Tn[4];
+        uint32_t f = sample_vmf(M, seed, (uint32_t)i, c1, c2, Tn);
+        if (f) {
+            flags |= f;
+            continue;
+        }
+        double logr = block_log_marginal(beta, S, Tn) - block_log_marginal(beta, S, T) +
+                      half_tr(T, M) - half_tr(Tn, M);
+        double ua, ub;
+        draw2(seed, (uint32_t)i, c1, c2, 3u, &ua, &ub);
+        if (log(ua) < logr) {
+            memcpy(T, Tn, sizeof Tn);
+            acc += 1;
+        }
+        for (int d = 0; d < 6; ++d) {
+            int64_t o;
+            double X[4], Y[4], V[4], Un[4];
+            block_neighbour(n, U, i, d, &o, X, Y);
+            or_staple(n, U, o, 3, V);
+            double Vb[4] = {beta * V[0], beta * V[1], beta * V[2], beta * V[3]};
+            uint32_t g = sample_vmf(Vb, seed, (uint32_t)o, c1, c2, Un);
+            if (g)
+                flags |= g;
+            else
+                memcpy(U + (o * 4 + 3) * 4, Un, sizeof Un);
+        }
+    }
+    if (accepted)
+        *accepted += acc;
+    return flags;
+}
+
+/* A sweep of block moves: centre parity 0 then 1, colours 0..7. */
+uint32_t or_block_sweep(const int n[4], double *U, double beta, uint64_t seed, uint32_t step, const double *y,
+                        uint32_t lattice_id, int64_t *accepted)
+{
+    uint32_t flags = 0;
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < 8; ++k)
+            flags |= or_block_move(n, U, beta, seed, step, p, k, y, lattice_id, accepted);
+    return flags;
+}

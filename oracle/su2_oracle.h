@@ -84,6 +84,22 @@ int or_polyakov_corr(const int n[4], const double *U, double *C);
 /* Random gauge transformation U_mu(x) -> g(x) U_mu(x) g(x+mu)^dagger. */
 void or_gauge_transform(const int n[4], double *U, uint64_t seed, uint32_t lattice_id);
 
+/* Learned block proposal (reference): Bessel functions, the block pieces
+ * S_o, the marginal log density of a block centre, the proposal's effective
+ * staple, and the move itself (see su2_oracle.c). */
+double or_bessel_ive(int n, double x);
+double or_log_z(double a);
+double or_bessel_ratio(double a);
+int or_block_colour(int x, int y, int z);
+void or_block_piece(const int n[4], const double *U, int64_t e, int dir, double S[4]);
+double or_block_log_marginal(const int n[4], const double *U, int64_t e, double beta, const double T[4]);
+void or_block_proposal(const int n[4], const double *U, int64_t e, double beta, const double y[6],
+                       double M[4]);
+uint32_t or_block_move(const int n[4], double *U, double beta, uint64_t seed, uint32_t step, int p, int k,
+                       const double *y, uint32_t lattice_id, int64_t *accepted);
+uint32_t or_block_sweep(const int n[4], double *U, double beta, uint64_t seed, uint32_t step, const double *y,
+                        uint32_t lattice_id, int64_t *accepted);
+
 /* Number of OpenMP threads the oracle's parallel loops use. */
 int or_num_threads(void);
 
