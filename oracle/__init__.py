@@ -61,6 +61,7 @@ def lib():
             "or_block_log_marginal": (dbl, [i4, dp, i64, dbl, dp]),
             "or_block_proposal": (None, [i4, dp, i64, dbl, dp, dp]),
             "or_block_move": (u32, [i4, dp, dbl, u64, u32, i32, i32, dp, u32, ctypes.POINTER(ctypes.c_int64)]),
+            "or_block_pieces_all": (None, [i4, dp, dp]),
             "or_block_sweep": (u32, [i4, dp, dbl, u64, u32, dp, u32, ctypes.POINTER(ctypes.c_int64)]),
         }
         for name, (res, args) in sig.items():
@@ -279,3 +280,12 @@ def block_sweep(n, U, beta, seed, step, y=None, lattice_id=0):
     acc = ctypes.c_int64(0)
     f = lib().or_block_sweep(_dims(n), _dp(U), beta, seed, step, _dp(y), lattice_id, ctypes.byref(acc))
     return f, acc.value
+
+
+def block_pieces_all(n, U):
+    """S[t, z, y, x, d, 4]: the block pieces of every site."""
+    _check_links(n, U)
+    nx, ny, nz, nt = n
+    S = np.empty((nt, nz, ny, nx, 6, 4))
+    lib().or_block_pieces_all(_dims(n), _dp(U), _dp(S))
+    return S

@@ -820,3 +820,13 @@ uint32_t or_block_sweep(const int n[4], double *U, double beta, uint64_t seed, u
             flags |= or_block_move(n, U, beta, seed, step, p, k, y, lattice_id, accepted);
     return flags;
 }
+
+/* Block pieces of every site: S[(site*6 + dir)*4 + k]. */
+void or_block_pieces_all(const int n[4], const double *U, double *S)
+{
+    int64_t vol = or_volume(n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < vol; ++i)
+        for (int d = 0; d < 6; ++d)
+            or_block_piece(n, U, i, d, S + (i * 6 + d) * 4);
+}

@@ -97,6 +97,7 @@ void or_block_proposal(const int n[4], const double *U, int64_t e, double beta, 
                        double M[4]);
 uint32_t or_block_move(const int n[4], double *U, double beta, uint64_t seed, uint32_t step, int p, int k,
                        const double *y, uint32_t lattice_id, int64_t *accepted);
+void or_block_pieces_all(const int n[4], const double *U, double *S);
 uint32_t or_block_sweep(const int n[4], double *U, double beta, uint64_t seed, uint32_t step, const double *y,
                         uint32_t lattice_id, int64_t *accepted);
 
