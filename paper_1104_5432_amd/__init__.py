@@ -68,6 +68,15 @@ _SIGNATURES = {
                                                 _VP]),
     "su2_batch_overrelax": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, ctypes.c_int32, _VP]),
     "su2_sweep_advance": (ctypes.c_int, [_VP, _VP]),
+    "su2_lp_param_count": (ctypes.c_int32, []),
+    "su2_lp_workspace_bytes": (ctypes.c_uint64, [_I4]),
+    "su2_lp_forward": (ctypes.c_int, [_LP, _VP, _VP, ctypes.c_uint64, _VP, _VP]),
+    "su2_lp_loss_grad": (ctypes.c_int, [_LP, ctypes.c_double, _VP, _VP, ctypes.c_uint64, _VP, _VP, _VP]),
+    "su2_lp_adam": (ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP]),
+    "su2_lp_move": (ctypes.c_int, [_LP, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
+                                   ctypes.c_int32, _VP, _VP, _VP]),
+    "su2_lp_sweep": (ctypes.c_int, [_LP, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, _VP, _VP, _VP]),
     "su2_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "su2_last_error": (ctypes.c_char_p, []),
 }
@@ -247,6 +256,63 @@ def su2_batch_overrelax(batch, n_sweeps=1, stream=None):
 def su2_sweep_advance(d_sweep, stream=None):
     """d_sweep[0] += 1 on the device."""
     _check(lib.su2_sweep_advance(d_sweep.data_ptr(), _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# Learned block proposal
+# ---------------------------------------------------------------------------
+def su2_lp_param_count():
+    return int(lib.su2_lp_param_count())
+
+
+def su2_lp_workspace_bytes(n):
+    return int(lib.su2_lp_workspace_bytes(_dims(n)[1]))
+
+
+class LPWork:
+    """Device workspace of the proposal network for lattices of extents n."""
+
+    def __init__(self, n, device="cuda"):
+        nb = su2_lp_workspace_bytes(n)
+        if nb == 0:
+            raise Su2Error(SU2_EDIMS, "the learned proposal needs Nx, Ny, Nz multiples of 8")
+        self.n = tuple(int(v) for v in n)
+        self.buf = torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def su2_lp_forward(lat, params, lpwork, y=None, stream=None):
+    """Network outputs y[site*6 + d] (device float32) for the current links."""
+    if y is None:
+        y = torch.empty(lat.volume * 6, dtype=torch.float32, device=lat.device)
+    _check(lib.su2_lp_forward(lat.ref(), params.data_ptr(), lpwork.buf.data_ptr(), lpwork.buf.numel(),
+                              y.data_ptr(), _stream(stream)))
+    return y
+
+
+def su2_lp_loss_grad(lat, beta, params, lpwork, grad=None, loss=None, stream=None):
+    if grad is None:
+        grad = torch.empty(su2_lp_param_count(), dtype=torch.float32, device=lat.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=lat.device)
+    _check(lib.su2_lp_loss_grad(lat.ref(), float(beta), params.data_ptr(), lpwork.buf.data_ptr(),
+                                lpwork.buf.numel(), grad.data_ptr(), loss.data_ptr(), _stream(stream)))
+    return grad, loss
+
+
+def su2_lp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib.su2_lp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), params.numel(),
+                           int(step), float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def su2_lp_move(lat, beta, seed, step, parity, colour, y, accepted, stream=None):
+    _check(lib.su2_lp_move(lat.ref(), float(beta), int(seed), int(step), int(parity), int(colour), y.data_ptr(),
+                           accepted.data_ptr(), _stream(stream)))
+
+
+def su2_lp_sweep(lat, beta, seed, step, y, accepted, stream=None):
+    """All 16 block classes with network outputs y; accepted[0] += accepted moves."""
+    _check(lib.su2_lp_sweep(lat.ref(), float(beta), int(seed), int(step), y.data_ptr(), accepted.data_ptr(),
+                            _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

@@ -2,6 +2,7 @@
 // before any HIP call), workspace layout, launch sequencing, error codes.
 #include "su2.h"
 #include "su2_launch.hpp"
+#include "su2_learned.hpp"
 
 #include <cmath>
 #include <cstdio>
@@ -369,6 +370,126 @@ int su2_sweep_advance(uint32_t *d_sweep, void *stream)
     if (!aligned(d_sweep, 4))
         return fail(SU2_EALIGN, "d_sweep must be 4-byte aligned");
     su2::launch_sweep_advance(d_sweep, (hipStream_t)stream);
+    return launched();
+}
+
+int32_t su2_lp_param_count(void)
+{
+    return su2::lp::param_count();
+}
+
+static bool lp_dims_ok(const int32_t n[4])
+{
+    return dims_ok(n) && n[0] % 8 == 0 && n[1] % 8 == 0 && n[2] % 8 == 0;
+}
+
+uint64_t su2_lp_workspace_bytes(const int32_t n[4])
+{
+    if (!lp_dims_ok(n))
+        return 0;
+    return su2::lp::work_layout(n).total;
+}
+
+static int check_lp(const su2_lattice_t *lat, su2::LaunchArgs *a)
+{
+    int rc = check_lattice(lat, a, nullptr);
+    if (rc)
+        return rc;
+    if (!lp_dims_ok(lat->n))
+        return fail(SU2_EDIMS, "the learned proposal needs Nx, Ny, Nz multiples of 8");
+    return SU2_OK;
+}
+
+static int check_lpwork(const su2_lattice_t *lat, const float *d_params, const void *d_lpwork, uint64_t bytes)
+{
+    if (!d_params || !d_lpwork)
+        return fail(SU2_EINVAL, "d_params and d_lpwork must be non-NULL device pointers");
+    if (!aligned(d_params, 4) || !aligned(d_lpwork, 16))
+        return fail(SU2_EALIGN, "d_params must be 4-byte and d_lpwork 16-byte aligned");
+    if (bytes < su2::lp::work_layout(lat->n).total)
+        return fail(SU2_EWORK, "lpwork_bytes is smaller than su2_lp_workspace_bytes()");
+    return SU2_OK;
+}
+
+int su2_lp_forward(const su2_lattice_t *lat, const float *d_params, void *d_lpwork, uint64_t lpwork_bytes,
+                   float *d_y, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lp(lat, &a);
+    if (!rc)
+        rc = check_lpwork(lat, d_params, d_lpwork, lpwork_bytes);
+    if (rc)
+        return rc;
+    if (!d_y || !aligned(d_y, 4))
+        return fail(SU2_EINVAL, "d_y must be a 4-byte aligned device pointer");
+    su2::lp::launch_forward(a, d_params, static_cast<char *>(d_lpwork), d_y, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_lp_loss_grad(const su2_lattice_t *lat, double beta, const float *d_params, void *d_lpwork,
+                     uint64_t lpwork_bytes, float *d_grad, double *d_loss, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lp(lat, &a);
+    if (!rc)
+        rc = check_lpwork(lat, d_params, d_lpwork, lpwork_bytes);
+    if (!rc)
+        rc = check_beta(beta);
+    if (rc)
+        return rc;
+    if (!d_grad || !d_loss || !aligned(d_grad, 4) || !aligned(d_loss, 8))
+        return fail(SU2_EINVAL, "d_grad and d_loss must be aligned device pointers");
+    su2::lp::launch_loss_grad(a, beta, d_params, static_cast<char *>(d_lpwork), d_grad, d_loss,
+                              (hipStream_t)stream);
+    return launched();
+}
+
+int su2_lp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int32_t count, int32_t step, float lr,
+                float beta1, float beta2, float eps, void *stream)
+{
+    if (!d_params || !d_grad || !d_m || !d_v)
+        return fail(SU2_EINVAL, "Adam needs four device arrays");
+    if (count < 1 || step < 1 || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+        !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(SU2_EINVAL, "bad Adam hyper-parameters (count >= 1, step >= 1, 0 <= beta < 1, eps > 0)");
+    su2::lp::launch_adam(d_params, d_grad, d_m, d_v, (uint32_t)count, step, lr, beta1, beta2, eps,
+                         (hipStream_t)stream);
+    return launched();
+}
+
+int su2_lp_move(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t step, int32_t parity, int32_t colour,
+                const float *d_y, uint32_t *d_accepted, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lp(lat, &a);
+    if (!rc)
+        rc = check_beta(beta);
+    if (rc)
+        return rc;
+    if ((parity != 0 && parity != 1) || colour < 0 || colour > 7 || step >= (1u << 28))
+        return fail(SU2_EINVAL, "parity 0/1, colour 0..7, step < 2^28");
+    if (!d_y || !d_accepted || !aligned(d_y, 4) || !aligned(d_accepted, 4))
+        return fail(SU2_EINVAL, "d_y and d_accepted must be aligned device pointers");
+    su2::lp::launch_block_move(a, beta, seed, step, parity, colour, d_y, d_accepted, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_lp_sweep(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t step, const float *d_y,
+                 uint32_t *d_accepted, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lp(lat, &a);
+    if (!rc)
+        rc = check_beta(beta);
+    if (rc)
+        return rc;
+    if (step >= (1u << 28))
+        return fail(SU2_EINVAL, "step < 2^28");
+    if (!d_y || !d_accepted || !aligned(d_y, 4) || !aligned(d_accepted, 4))
+        return fail(SU2_EINVAL, "d_y and d_accepted must be aligned device pointers");
+    for (int p = 0; p < 2; ++p)
+        for (int k = 0; k < 8; ++k)
+            su2::lp::launch_block_move(a, beta, seed, step, p, k, d_y, d_accepted, (hipStream_t)stream);
     return launched();
 }
 

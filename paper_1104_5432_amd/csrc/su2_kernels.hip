@@ -14,42 +14,6 @@ namespace su2 {
 constexpr int kBlock = 256;
 
 // ---------------------------------------------------------------------------
-// Staple sum of U_mu(x) (x of parity `par`, checkerboard index cb):
-//   V = sum_{nu != mu} U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
-//                    + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
-// so that the link's local action is -(beta/2) Tr(U_mu(x) V).
-// ---------------------------------------------------------------------------
-template <class T, int MU>
-__device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, const Site &s, uint32_t cb,
-                                          int par)
-{
-    const int opp = par ^ 1;
-    const uint32_t cb_xp = cb_shift(g, s.c, MU == 0, MU == 1, MU == 2, MU == 3);
-    Quat<T> V = {0, 0, 0, 0};
-#pragma unroll
-    for (int nu = 0; nu < 4; ++nu) {
-        if (nu == MU)
-            continue;
-        const int32_t e0 = (nu == 0), e1 = (nu == 1), e2 = (nu == 2), e3 = (nu == 3);
-        const int32_t m0 = (MU == 0), m1 = (MU == 1), m2 = (MU == 2), m3 = (MU == 3);
-        const uint32_t cb_xpn = cb_shift(g, s.c, e0, e1, e2, e3);
-        const uint32_t cb_xmn = cb_shift(g, s.c, -e0, -e1, -e2, -e3);
-        const uint32_t cb_xpmn = cb_shift(g, s.c, m0 - e0, m1 - e1, m2 - e2, m3 - e3);
-        // upper staple
-        const Quat<T> a = U.ld(nu, opp, cb_xp);
-        const Quat<T> b = U.ld(MU, opp, cb_xpn);
-        const Quat<T> c = U.ld(nu, par, cb);
-        qacc(V, qmul_nd(qmul_nd(a, b), c));
-        // lower staple
-        const Quat<T> d = U.ld(nu, par, cb_xpmn);
-        const Quat<T> e = U.ld(MU, opp, cb_xmn);
-        const Quat<T> f = U.ld(nu, opp, cb_xmn);
-        qacc(V, qmul(qmul_dd(d, e), f));
-    }
-    return V;
-}
-
-// ---------------------------------------------------------------------------
 // Heat bath for one class.  With k = |V|, Vhat = V/k and alpha = beta k, the
 // new link is W Vhat^dagger where W has density ~ exp(alpha w0) w.r.t. Haar
 // measure: w0 by Kennedy-Pendleton (alpha >= 2) or Creutz (alpha < 2), the
