@@ -16,6 +16,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -41,7 +43,9 @@ def parse():
                     help="walk of the single lattice: 0 default strip, > 0 strip width, < 0 plain order")
     ap.add_argument("--autotune", action="store_true",
                     help="choose the walk with paper_1104_5432_amd.autotune before timing (untimed)")
-    ap.add_argument("--workload", choices=["single", "scan"], default="single",
+    ap.add_argument("--train", type=int, default=10000,
+                    help="learned workload: heat-bath configurations to train on")
+    ap.add_argument("--workload", choices=["single", "scan", "learned"], default="single",
                     help="single: one lattice (--shape); scan: 16 lattices mixing 32^3x4, 48^3x6, "
                          "64^3x8 at beta 2.2..2.7, one captured graph replay per sweep")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -186,6 +190,71 @@ def scan(args):
     print(json.dumps(rec), flush=True)
 
 
+def learned_workload(args):
+    """Learned proposal at 16^3 x 4, beta 2.30 (near deconfinement): train the
+    network on args.train heat-bath configurations, then compare chains of
+    args.steps sweeps -- heat bath; heat bath + 4 overrelaxation; heat bath +
+    one learned sweep (trained, and untrained = mean-field coefficients) --
+    by the integrated autocorrelation time of the Polyakov loop |L| and by
+    effective independent samples per second, N / (2 tau_int) / wall time."""
+    import torch
+    from paper_1104_5432_amd import learned
+    from paper_1104_5432_amd.stats import gamma_method
+
+    n, beta, seed = (16, 16, 16, 4), 2.30, args.seed
+    lat = learned.thermalised_lattice(n, beta, seed, 500, prec=args.prec)
+    t0 = time.perf_counter()
+    params, losses = learned.train(lat, beta, seed, args.train, first_sweep=500)
+    t_train = time.perf_counter() - t0
+    untrained = learned.init_params(seed)
+    chains = {}
+    for name, prm, n_or in (("heatbath", None, 0), ("heatbath+4or", None, 4),
+                            ("heatbath+learned", params, 0), ("heatbath+untrained", untrained, 0)):
+        c = learned.thermalised_lattice(n, beta, seed + 7, 500, prec=args.prec)
+        r = learned.run_chain(c, beta, seed + 7, args.steps, params=prm, n_or=n_or, first_sweep=500)
+        absl = np.abs(np.array(r["polyakov"]))
+        m, err, tau, _ = gamma_method(absl)
+        ms, es, taus, _ = gamma_method(np.array(r["polyakov"]))
+        mp, ep, taup, _ = gamma_method(np.array(r["plaquette"]))
+        chains[name] = {
+            "tau_int_abs_polyakov": tau, "abs_polyakov": m, "abs_polyakov_err": err,
+            "tau_int_polyakov": taus, "tau_int_plaquette": taup, "plaquette": mp, "plaquette_err": ep,
+            "acceptance": r["acceptance"], "wall_s": r["wall_s"], "ms_per_sweep": 1e3 * r["wall_s"] / args.steps,
+            "eff_samples_per_s": args.steps / (2 * tau) / r["wall_s"],
+            "eff_samples_per_sweep": 1.0 / (2 * tau),
+        }
+        print(f"{name}: {chains[name]}", file=sys.stderr, flush=True)
+    rec = {
+        "metric": METRIC,
+        "value": chains["heatbath+learned"]["eff_samples_per_s"],
+        "unit": "eff. indep. Polyakov samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 500,
+        "ms_per_step": chains["heatbath+learned"]["ms_per_sweep"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": "learned proposal: SU(2) 16^3x4, beta 2.30, hot start, network trained on "
+                        f"{args.train} heat-bath configurations; chains of {args.steps} sweeps compared by "
+                        "tau_int of |Polyakov loop|",
+            "train_configs": args.train,
+            "train_s": t_train,
+            "loss_first_100": float(np.mean(losses[:100])),
+            "loss_last_100": float(np.mean(losses[-100:])),
+        },
+        "chains": chains,
+        "gain_vs_heatbath_per_s": chains["heatbath+learned"]["eff_samples_per_s"]
+                                  / chains["heatbath"]["eff_samples_per_s"],
+        "gain_vs_untrained_per_s": chains["heatbath+learned"]["eff_samples_per_s"]
+                                   / chains["heatbath+untrained"]["eff_samples_per_s"],
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -194,6 +263,9 @@ def main():
         sys.exit(2)
     if args.workload == "scan":
         scan(args)
+        return
+    if args.workload == "learned":
+        learned_workload(args)
         return
 
     import torch

@@ -1,8 +1,6 @@
 import os
 import sys
 
-import pytest
-
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -11,3 +9,13 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: statistical test taking more than a few seconds")
+    # the package loads libsu2.so on import; build it once if nothing is built
+    # (build.py is loaded by path: importing it through the package would load
+    # the library first)
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_su2_build", os.path.join(ROOT, "paper_1104_5432_amd", "build.py"))
+    hip_build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(hip_build)
+    if not os.path.exists(hip_build.LIB):
+        hip_build.build()

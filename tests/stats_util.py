@@ -1,9 +1,7 @@
 """Statistics used by the statistical pins and the FP32-versus-FP64 checks.
 
-- gamma_method: error of a Monte Carlo mean with its integrated
-  autocorrelation time, by the Gamma method of U. Wolff, "Monte Carlo errors
-  with less errors", Comput. Phys. Commun. 156 (2004) 143, with the automatic
-  summation window (S = 1.5) and the bias correction described there.
+- gamma_method: re-exported from paper_1104_5432_amd.stats (Wolff's Gamma
+  method), pinned in tests/test_stats.py.
 - x0_cdf: the exact conditional distribution function of w0 = (1/2)Tr(W)
   when W has density ~ exp(alpha w0) with respect to Haar measure on SU(2),
   i.e. w0 has density ~ sqrt(1 - w0^2) exp(alpha w0) on [-1, 1].  Computed
@@ -16,38 +14,7 @@ import numpy as np
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(96)
 
 
-def gamma_method(a, S=1.5):
-    """Return (mean, error, tau_int, window) of the series a."""
-    a = np.asarray(a, dtype=np.float64)
-    N = a.size
-    mean = a.mean()
-    d = a - mean
-    gamma0 = np.dot(d, d) / N
-    if gamma0 == 0.0:
-        return mean, 0.0, 0.5, 0
-    tmax = N // 2
-    gam = np.empty(tmax + 1)
-    gam[0] = gamma0
-    for t in range(1, tmax + 1):
-        gam[t] = np.dot(d[:N - t], d[t:]) / (N - t)
-    window = tmax
-    tau_w = 0.5
-    for W in range(1, tmax + 1):
-        tau_w = 0.5 + gam[1:W + 1].sum() / gamma0
-        if tau_w <= 0.5:
-            window = W
-            break
-        tau = S / np.log((2 * tau_w + 1) / (2 * tau_w - 1))
-        g = np.exp(-W / tau) - tau / np.sqrt(W * N)
-        if g < 0:
-            window = W
-            break
-    # bias correction of the estimated Gamma(0) and tau_int
-    c_total = gamma0 + 2 * gam[1:window + 1].sum()
-    c_total *= 1.0 + (2 * window + 1) / N
-    tau_int = max(c_total / (2 * gamma0), 0.5)
-    err = np.sqrt(max(c_total, 0.0) / N)
-    return mean, err, tau_int, window
+from paper_1104_5432_amd.stats import gamma_method  # noqa: E402,F401  (pinned in test_stats.py)
 
 
 def _x0_unnormalised(alpha, w):

@@ -179,3 +179,29 @@ def test_learned_chain_is_exact(su2):
         z = (mb - ma) / np.hypot(ea, eb)
         print(f"{key}: hb {ma:.5f}({ea:.5f}) learned {mb:.5f}({eb:.5f}) z = {z:+.2f}", flush=True)
         assert abs(z) <= 3.0
+
+
+@pytest.mark.slow
+def test_training_beats_the_untrained_network(su2):
+    # The method without the trained network is the same block move with
+    # y = 0 (mean-field coefficients).  Training on heat-bath configurations
+    # must lower the held-out loss and raise the acceptance.
+    from paper_1104_5432_amd import learned
+    n, beta = (16, 16, 16, 4), 2.3
+    lat = learned.thermalised_lattice(n, beta, 5, 300, prec="f32")
+    params, losses = learned.train(lat, beta, 5, 1500, first_sweep=300, lr=2e-3)
+    untrained = learned.init_params(5)
+    work = su2.LPWork(n)
+    held = {"trained": [], "untrained": []}
+    for s in range(20):
+        su2.su2_heatbath_sweep(lat, beta, 6, 5000 + s)
+        for name, prm in (("trained", params), ("untrained", untrained)):
+            _, loss = su2.su2_lp_loss_grad(lat, beta, prm, work)
+            held[name].append(loss.item())
+    assert np.mean(held["trained"]) < np.mean(held["untrained"]), held
+    acc = {}
+    for name, prm in (("trained", params), ("untrained", untrained)):
+        c = learned.thermalised_lattice(n, beta, 8, 100, prec="f32")
+        acc[name] = learned.run_chain(c, beta, 8, 60, params=prm, first_sweep=100)["acceptance"]
+    print(f"acceptance {acc}", flush=True)
+    assert acc["trained"] > acc["untrained"] + 0.005, acc
