@@ -209,15 +209,18 @@ def learned_workload(args):
     untrained = learned.init_params(seed)
     chains = {}
     for name, prm, n_or in (("heatbath", None, 0), ("heatbath+4or", None, 4),
-                            ("heatbath+learned", params, 0), ("heatbath+untrained", untrained, 0)):
+                            ("heatbath+learned", params, 0), ("heatbath+untrained", untrained, 0),
+                            ("heatbath+4or+learned", params, 4)):
         c = learned.thermalised_lattice(n, beta, seed + 7, 500, prec=args.prec)
         r = learned.run_chain(c, beta, seed + 7, args.steps, params=prm, n_or=n_or, first_sweep=500)
         absl = np.abs(np.array(r["polyakov"]))
-        m, err, tau, _ = gamma_method(absl)
+        m, err, tau, win = gamma_method(absl)
+        dtau = tau * np.sqrt(2.0 * (2 * win + 1) / args.steps)     # Wolff (2004), eq. (42)
         ms, es, taus, _ = gamma_method(np.array(r["polyakov"]))
         mp, ep, taup, _ = gamma_method(np.array(r["plaquette"]))
         chains[name] = {
-            "tau_int_abs_polyakov": tau, "abs_polyakov": m, "abs_polyakov_err": err,
+            "tau_int_abs_polyakov": tau, "tau_int_abs_polyakov_err": dtau,
+            "abs_polyakov": m, "abs_polyakov_err": err,
             "tau_int_polyakov": taus, "tau_int_plaquette": taup, "plaquette": mp, "plaquette_err": ep,
             "acceptance": r["acceptance"], "wall_s": r["wall_s"], "ms_per_sweep": 1e3 * r["wall_s"] / args.steps,
             "eff_samples_per_s": args.steps / (2 * tau) / r["wall_s"],

@@ -146,16 +146,17 @@ __device__ __forceinline__ Quat<double> temporal_staple(const Links<T> &U, const
 }
 
 // Piece S_o of centre e for direction d (0..5 = -x,+x,-y,+y,-z,+z); also
-// returns the neighbour's site.
+// returns the neighbour's site, the factors X, Y of its staple's term
+// through e (X T(e)^+ Y) and the rest of that staple, V_o - X T(e)^+ Y.
 template <class T>
 __device__ __forceinline__ Quat<double> block_piece(const Links<T> &U, const Geom &g, uint32_t e,
-                                                    const Quat<double> &Te, int d, uint32_t &o)
+                                                    const Quat<double> &Te, int d, uint32_t &o, Quat<double> &X,
+                                                    Quat<double> &Y, Quat<double> &Vrest)
 {
     const Coord ce = coord_of(g, e);
     const int i = d >> 1;
     const int sgn = (d & 1) ? 1 : -1;
     o = shifted(g, ce, i, sgn);
-    Quat<double> X, Y;
     if (sgn < 0) {
         // e = o + i: the upper term U_i(o+t) T(e)^+ U_i(o)^+
         const Coord co = coord_of(g, o);
@@ -168,10 +169,18 @@ __device__ __forceinline__ Quat<double> block_piece(const Links<T> &U, const Geo
         X = {a.w, -a.x, -a.y, -a.z};
         Y = load_d(U, i, e, g);
     }
-    Quat<double> V = temporal_staple(U, g, o);
+    const Quat<double> V = temporal_staple(U, g, o);
     const Quat<double> term = qmul(qmul_nd(X, Te), Y);
-    V = {V.w - term.w, V.x - term.x, V.y - term.y, V.z - term.z};
-    return qmul_nd(qmul_dn(X, V), Y);   // X^+ V Y^+
+    Vrest = {V.w - term.w, V.x - term.x, V.y - term.y, V.z - term.z};
+    return qmul_nd(qmul_dn(X, Vrest), Y);   // X^+ Vrest Y^+
+}
+
+template <class T>
+__device__ __forceinline__ Quat<double> block_piece(const Links<T> &U, const Geom &g, uint32_t e,
+                                                    const Quat<double> &Te, int d, uint32_t &o)
+{
+    Quat<double> X, Y, Vrest;
+    return block_piece(U, g, e, Te, d, o, X, Y, Vrest);
 }
 
 __device__ __forceinline__ double half_tr(const Quat<double> &a, const Quat<double> &b)
@@ -246,68 +255,111 @@ __device__ __forceinline__ bool sample_vmf(const Quat<double> &M, uint32_t c0, u
 }
 
 // ---------------------------------------------------------------------------
-// Block move for centres of parity p and colour k, every slice.
+// Block move for centres of parity p and colour k, every slice.  A team of 8
+// lanes takes one centre: lane d < 6 handles direction d (its piece,
+// coefficient, marginal term and the redraw of its neighbour), M and the
+// log acceptance ratio are summed over the team with xor shuffles, lane 0
+// samples the proposal and takes the decision.
 // ---------------------------------------------------------------------------
+template <class V>
+__device__ __forceinline__ V team_sum(V v)
+{
+    v += __shfl_xor(v, 1, 8);
+    v += __shfl_xor(v, 2, 8);
+    v += __shfl_xor(v, 4, 8);
+    return v;
+}
+
+__device__ __forceinline__ Quat<double> team_sum(const Quat<double> &q)
+{
+    return {team_sum(q.w), team_sum(q.x), team_sum(q.y), team_sum(q.z)};
+}
+
+__device__ __forceinline__ Quat<double> team_bcast(const Quat<double> &q)
+{
+    return {__shfl(q.w, 0, 8), __shfl(q.x, 0, 8), __shfl(q.y, 0, 8), __shfl(q.z, 0, 8)};
+}
+
 template <class T>
 __global__ __launch_bounds__(64) void block_move_kernel(Links<T> U, Geom g, double beta, uint32_t k0, uint32_t k1,
                                                          uint32_t c1, uint32_t c2, int p, int colour,
                                                          const float *y, uint32_t *accepted, uint32_t *flags)
 {
     const uint32_t per_slice = g.vs / 16u;
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= per_slice * (uint32_t)g.n[3])
-        return;
-    const uint32_t t = j / per_slice;
-    uint32_t rem = j - t * per_slice;
-    const uint32_t nx8 = (uint32_t)g.n[0] / 8u, ny2 = (uint32_t)g.n[1] / 2u;
-    const uint32_t xi = rem % nx8;
-    rem /= nx8;
-    const uint32_t yi = rem % ny2;
-    const uint32_t z = rem / ny2;
-    const int32_t yy = (int32_t)(2u * yi + (uint32_t)((p + colour) & 1));
-    const int32_t x0 = (((colour - 2 * yy - 3 * (int32_t)z) % 8) + 8) % 8;
-    const int32_t xx = x0 + 8 * (int32_t)xi;
-    const uint32_t e = site_at(g, xx, yy, (int32_t)z, (int32_t)t);
+    const uint32_t count = per_slice * (uint32_t)g.n[3];
+    const uint32_t j = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int d = (int)(threadIdx.x & 7u);
+    const bool centre_ok = j < count;
+    const bool lane_ok = centre_ok && d < 6;
 
-    const Quat<double> Te = load_d(U, 3, e, g);
-    Quat<double> S[6];
-    double s2[6];
-    Quat<double> M = {0.0, 0.0, 0.0, 0.0};
-    for (int d = 0; d < 6; ++d) {
-        uint32_t o;
-        S[d] = block_piece(U, g, e, Te, d, o);
-        s2[d] = qdot4(S[d], S[d]);
-        const double c = mean_field_coefficient(beta, s2[d]) * exp((double)y[(size_t)e * 6 + d]);
-        M = {M.w + c * S[d].w, M.x + c * S[d].x, M.y + c * S[d].y, M.z + c * S[d].z};
+    uint32_t e = 0;
+    if (centre_ok) {
+        const uint32_t t = j / per_slice;
+        uint32_t rem = j - t * per_slice;
+        const uint32_t nx8 = (uint32_t)g.n[0] / 8u, ny2 = (uint32_t)g.n[1] / 2u;
+        const uint32_t xi = rem % nx8;
+        rem /= nx8;
+        const uint32_t yi = rem % ny2;
+        const uint32_t z = rem / ny2;
+        const int32_t yy = (int32_t)(2u * yi + (uint32_t)((p + colour) & 1));
+        const int32_t x0 = (((colour - 2 * yy - 3 * (int32_t)z) % 8) + 8) % 8;
+        e = site_at(g, x0 + 8 * (int32_t)xi, yy, (int32_t)z, (int32_t)t);
     }
-    Quat<double> Tn;
-    if (!sample_vmf(M, e, c1, c2, k0, k1, Tn)) {
-        atomicOr(flags, kFlagCap);
-        return;
+    const Quat<double> Te = centre_ok ? load_d(U, 3, e, g) : Quat<double>{1.0, 0.0, 0.0, 0.0};
+
+    Quat<double> S = {0, 0, 0, 0}, X = {1, 0, 0, 0}, Y = {1, 0, 0, 0}, Vrest = {0, 0, 0, 0};
+    double s2 = 0.0, c = 0.0;
+    uint32_t o = 0;
+    if (lane_ok) {
+        S = block_piece(U, g, e, Te, d, o, X, Y, Vrest);
+        s2 = qdot4(S, S);
+        c = mean_field_coefficient(beta, s2) * exp((double)y[(size_t)e * 6 + d]);
     }
-    double logr = half_tr(Te, M) - half_tr(Tn, M);
-    for (int d = 0; d < 6; ++d) {
-        const double vn = s2[d] + 1.0 + 2.0 * half_tr(Tn, S[d]);
-        const double vo = s2[d] + 1.0 + 2.0 * half_tr(Te, S[d]);
-        logr += log_z(beta * sqrt(fmax(vn, 0.0))) - log_z(beta * sqrt(fmax(vo, 0.0)));
+    const Quat<double> M = team_sum(Quat<double>{c * S.w, c * S.x, c * S.y, c * S.z});
+
+    Quat<double> Tn = Te;
+    int ok = 1;
+    if (d == 0 && centre_ok)
+        ok = sample_vmf(M, e, c1, c2, k0, k1, Tn) ? 1 : 0;
+    Tn = team_bcast(Tn);
+    ok = __shfl(ok, 0, 8);
+
+    double part = 0.0;
+    if (lane_ok && ok) {
+        const double vn = s2 + 1.0 + 2.0 * half_tr(Tn, S);
+        const double vo = s2 + 1.0 + 2.0 * half_tr(Te, S);
+        part = log_z(beta * sqrt(fmax(vn, 0.0))) - log_z(beta * sqrt(fmax(vo, 0.0)));
     }
-    double ua, ub;
-    Draw<double>::two(philox(e, c1, c2, 3u, k0, k1), ua, ub);
-    if (log(ua) < logr) {
-        store_d(U, 3, e, g, Tn);
-        atomicAdd(accepted, 1u);
-    }
-    const Coord ce = coord_of(g, e);
-    for (int d = 0; d < 6; ++d) {
-        const uint32_t o = shifted(g, ce, d >> 1, (d & 1) ? 1 : -1);
-        const Quat<double> V = temporal_staple(U, g, o);
-        const Quat<double> Vb = {beta * V.w, beta * V.x, beta * V.y, beta * V.z};
-        Quat<double> Un;
-        if (sample_vmf(Vb, o, c1, c2, k0, k1, Un))
-            store_d(U, 3, o, g, Un);
-        else
+    const double logmarg = team_sum(part);
+
+    int acc = 0;
+    if (d == 0 && centre_ok) {
+        if (!ok) {
             atomicOr(flags, kFlagCap);
+        } else {
+            const double logr = logmarg + half_tr(Te, M) - half_tr(Tn, M);
+            double ua, ub;
+            Draw<double>::two(philox(e, c1, c2, 3u, k0, k1), ua, ub);
+            if (log(ua) < logr) {
+                acc = 1;
+                store_d(U, 3, e, g, Tn);
+                atomicAdd(accepted, 1u);
+            }
+        }
     }
+    acc = __shfl(acc, 0, 8);
+    if (!lane_ok || !ok)
+        return;
+    // redraw the neighbour's temporal link given the centre's current link
+    const Quat<double> Tc = acc ? Tn : Te;
+    const Quat<double> term = qmul(qmul_nd(X, Tc), Y);
+    const Quat<double> Vb = {beta * (Vrest.w + term.w), beta * (Vrest.x + term.x), beta * (Vrest.y + term.y),
+                             beta * (Vrest.z + term.z)};
+    Quat<double> Un;
+    if (sample_vmf(Vb, o, c1, c2, k0, k1, Un))
+        store_d(U, 3, o, g, Un);
+    else
+        atomicOr(flags, kFlagCap);
 }
 
 // ---------------------------------------------------------------------------
@@ -823,7 +875,7 @@ void launch_block_move(const LaunchArgs &a, double beta, uint64_t seed, uint32_t
     const uint32_t c1 = 3u + 4u * 2u + 16u * (uint32_t)a.lattice_id;
     const uint32_t c2 = 16u * step + 8u * (uint32_t)parity + (uint32_t)colour;
     const uint32_t count = g.vs / 16u * (uint32_t)a.n[3];
-    const uint32_t blocks = (count + 63) / 64;
+    const uint32_t blocks = (count * 8u + 63) / 64;   // 8 lanes per centre
     if (a.prec == kF32)
         block_move_kernel<float><<<blocks, 64, 0, st>>>(links_of<float>(a), g, beta, k0, k1, c1, c2, parity, colour, y,
                                                         accepted, a.flags);
