@@ -164,9 +164,9 @@ __host__ inline FastDiv make_fastdiv(uint32_t d)
     return {d, (uint32_t)m, l};
 }
 
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
+__host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
 {
-    return (__umulhi(n, f.m) + n) >> f.l;
+    return ((uint32_t)(((uint64_t)n * f.m) >> 32) + n) >> f.l;
 }
 
 // Order in which the threads of one checkerboard class walk its V/2 sites.
@@ -206,8 +206,53 @@ struct BatchEntry {
     uint32_t lid16;   // 16 * lattice_id, the lattice's share of counter word c1
     uint32_t block0;  // first block of this lattice in the batched grid (multiple of 8)
     uint32_t nblocks; // blocks of this lattice (multiple of 8)
-    uint32_t unused;
+    uint32_t col;     // 1: the lattice qualifies for column addressing
 };
+
+// ---------------------------------------------------------------------------
+// Geometry construction (host).  Walk of a class: tile > 0 is the strip width
+// (it divides Nz; the caller checked), tile == 0 the default (Nz/8 rounded
+// down to a divisor of Nz, so that each of the 8 XCDs takes one strip),
+// tile < 0 plain cb order.  Every field is set in every mode.
+// ---------------------------------------------------------------------------
+__host__ inline int default_strip(const int32_t n[4])
+{
+    const uint32_t nz = (uint32_t)n[2];
+    uint32_t w = nz / 8u > 0 ? nz / 8u : 1u;
+    while (nz % w)
+        --w;
+    return (int)w;
+}
+
+__host__ inline BlockOrder make_block_order(const int32_t n[4], int tile)
+{
+    BlockOrder o = {};
+    o.cols = (uint32_t)n[0] / 2u * (uint32_t)n[1];
+    o.nz = (uint32_t)n[2];
+    o.div_cols = make_fastdiv(o.cols);
+    o.div_nt = make_fastdiv((uint32_t)n[3]);
+    const int w = tile == 0 ? default_strip(n) : tile;
+    o.strip = w > 0 ? (uint32_t)w : 0u;
+    o.div_w = make_fastdiv(w > 0 ? (uint32_t)w : 1u);
+    return o;
+}
+
+__host__ inline Geom make_geom(const int32_t n[4], int tile)
+{
+    Geom g = {};
+    for (int d = 0; d < 4; ++d)
+        g.n[d] = n[d];
+    g.nxh = (uint32_t)n[0] / 2u;
+    const uint64_t vol = (uint64_t)n[0] * n[1] * n[2] * n[3];
+    g.half = (uint32_t)(vol / 2);
+    g.vs = (uint32_t)((uint64_t)n[0] * n[1] * n[2]);
+    g.div_nx = make_fastdiv((uint32_t)n[0]);
+    g.div_nxh = make_fastdiv(g.nxh);
+    g.div_ny = make_fastdiv((uint32_t)n[1]);
+    g.div_nz = make_fastdiv((uint32_t)n[2]);
+    g.ord = make_block_order(n, tile);
+    return g;
+}
 
 struct Site {
     int32_t c[4];  // x, y, z, t
@@ -215,7 +260,7 @@ struct Site {
 };
 
 // Coordinates of the cb-th site of the given parity.
-__device__ __forceinline__ Site site_of_cb(const Geom &g, uint32_t cb, int parity)
+__host__ __device__ __forceinline__ Site site_of_cb(const Geom &g, uint32_t cb, int parity)
 {
     const uint32_t row = fdiv(cb, g.div_nxh);
     const uint32_t xh = cb - row * g.nxh;
@@ -233,13 +278,13 @@ __device__ __forceinline__ Site site_of_cb(const Geom &g, uint32_t cb, int parit
     return s;
 }
 
-__device__ __forceinline__ uint32_t cb_of(const Geom &g, int32_t x, int32_t y, int32_t z, int32_t t)
+__host__ __device__ __forceinline__ uint32_t cb_of(const Geom &g, int32_t x, int32_t y, int32_t z, int32_t t)
 {
     return ((uint32_t)x >> 1) +
            g.nxh * ((uint32_t)y + (uint32_t)g.n[1] * ((uint32_t)z + (uint32_t)g.n[2] * (uint32_t)t));
 }
 
-__device__ __forceinline__ int32_t wrap_add(int32_t c, int32_t s, int32_t n)
+__host__ __device__ __forceinline__ int32_t wrap_add(int32_t c, int32_t s, int32_t n)
 {
     c += s;
     c = (c >= n) ? c - n : c;
@@ -247,7 +292,7 @@ __device__ __forceinline__ int32_t wrap_add(int32_t c, int32_t s, int32_t n)
 }
 
 // cb index of the site displaced by (d0,d1,d2,d3) in {-1,0,1}.
-__device__ __forceinline__ uint32_t cb_shift(const Geom &g, const int32_t c[4], int32_t d0, int32_t d1,
+__host__ __device__ __forceinline__ uint32_t cb_shift(const Geom &g, const int32_t c[4], int32_t d0, int32_t d1,
                                              int32_t d2, int32_t d3)
 {
     return cb_of(g, wrap_add(c[0], d0, g.n[0]), wrap_add(c[1], d1, g.n[1]),
@@ -273,6 +318,18 @@ struct Links<float> {
     {
         p[(size_t)(2 * mu + par) * half + cb] = make_float4(q.w, q.x, q.y, q.z);
     }
+    // by byte offset within the plane (< 2^32)
+    __device__ __forceinline__ Quat<float> ldb(int mu, int par, uint32_t boff) const
+    {
+        const char *base = reinterpret_cast<const char *>(p + (size_t)(2 * mu + par) * half);
+        const float4 v = *reinterpret_cast<const float4 *>(base + boff);
+        return {v.x, v.y, v.z, v.w};
+    }
+    __device__ __forceinline__ void stb(int mu, int par, uint32_t boff, const Quat<float> &q) const
+    {
+        char *base = reinterpret_cast<char *>(p + (size_t)(2 * mu + par) * half);
+        *reinterpret_cast<float4 *>(base + boff) = make_float4(q.w, q.x, q.y, q.z);
+    }
 };
 
 template <>
@@ -291,6 +348,24 @@ struct Links<double> {
         const size_t q = (size_t)(2 * mu + par);
         p[(2 * q) * half + cb] = make_double2(v.w, v.x);
         p[(2 * q + 1) * half + cb] = make_double2(v.y, v.z);
+    }
+    // by byte offset within the sub-planes (< 2^32)
+    __device__ __forceinline__ Quat<double> ldb(int mu, int par, uint32_t boff) const
+    {
+        const size_t q = (size_t)(2 * mu + par);
+        const char *ba = reinterpret_cast<const char *>(p + (2 * q) * half);
+        const char *bb = reinterpret_cast<const char *>(p + (2 * q + 1) * half);
+        const double2 a = *reinterpret_cast<const double2 *>(ba + boff);
+        const double2 b = *reinterpret_cast<const double2 *>(bb + boff);
+        return {a.x, a.y, b.x, b.y};
+    }
+    __device__ __forceinline__ void stb(int mu, int par, uint32_t boff, const Quat<double> &v) const
+    {
+        const size_t q = (size_t)(2 * mu + par);
+        char *ba = reinterpret_cast<char *>(p + (2 * q) * half);
+        char *bb = reinterpret_cast<char *>(p + (2 * q + 1) * half);
+        *reinterpret_cast<double2 *>(ba + boff) = make_double2(v.w, v.x);
+        *reinterpret_cast<double2 *>(bb + boff) = make_double2(v.y, v.z);
     }
 };
 
@@ -311,7 +386,7 @@ __device__ __forceinline__ Quat<float> unitize<float>(const Quat<float> &q)
 // XCD-aware block order: consecutive blocks are dispatched round-robin over
 // the 8 XCDs, each with its own L2; renumber so that each XCD works through
 // one contiguous range of tiles (neighbouring tiles share halo links).
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks)
+__host__ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks)
 {
     const uint32_t q = nblocks >> 3, r = nblocks & 7u;
     const uint32_t xcd = b & 7u, k = b >> 3;
@@ -319,7 +394,7 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nblocks)
 }
 
 // cb index of the i-th site of the walk.
-__device__ __forceinline__ uint32_t walk_cb(uint32_t i, const BlockOrder &o)
+__host__ __device__ __forceinline__ uint32_t walk_cb(uint32_t i, const BlockOrder &o)
 {
     if (o.strip == 0)
         return i;
@@ -334,39 +409,181 @@ __device__ __forceinline__ uint32_t walk_cb(uint32_t i, const BlockOrder &o)
 }
 
 // ---------------------------------------------------------------------------
-// Staple sum of U_mu(x) (x of parity `par`, checkerboard index cb):
+// Addressing of a site's neighbours.  Two policies give the same indices:
+//
+// CbAddr: from the site's coordinates (cb_shift), for any geometry.
+//
+// ColAddr: when C = Nx Ny / 2 is a multiple of 64, the 64 sites of a wave lie
+// in one (z,t) column of the walk, so z, t and everything derived from them
+// are wave-uniform (scalar registers) and only the in-plane position varies
+// per lane.  A neighbour's index is then the sum of an x part and a y part
+// (per lane) and a z part and a t part (scalar), each precomputed for the
+// shifts 0, +1, -1.  Offsets are kept in bytes: with V/2 <= 2^28 a plane's
+// byte offsets fit 32 bits, so every load is a scalar plane base plus one
+// 32-bit lane offset (one add per load instead of the coordinate arithmetic).
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int shift_slot(int d)
+{
+    return d == 0 ? 0 : (d > 0 ? 1 : 2);
+}
+
+struct CbAddr {
+    Site s;
+    uint32_t cb;
+    const Geom *g;
+    __host__ __device__ __forceinline__ uint32_t at(int32_t d0, int32_t d1, int32_t d2, int32_t d3) const
+    {
+        if (d0 == 0 && d1 == 0 && d2 == 0 && d3 == 0)
+            return cb;
+        return cb_shift(*g, s.c, d0, d1, d2, d3);
+    }
+    template <class T>
+    __device__ __forceinline__ Quat<T> ld(const Links<T> &U, int mu, int par, uint32_t idx) const
+    {
+        return U.ld(mu, par, idx);
+    }
+    template <class T>
+    __device__ __forceinline__ void st(const Links<T> &U, int mu, int par, uint32_t idx, const Quat<T> &q) const
+    {
+        U.st(mu, par, idx, q);
+    }
+    __host__ __device__ __forceinline__ uint32_t site() const
+    {
+        return s.site;
+    }
+};
+
+struct ColAddr {
+    uint32_t xb[3]; // lane: 16 * (x' >> 1) for x' = x, x+1, x-1 (mod Nx)
+    uint32_t yb[3]; // lane: 16 * (Nx/2) * y' for y' = y, y+1, y-1 (mod Ny)
+    uint32_t zb[3]; // wave: 16 * C * z' for z' = z, z+1, z-1 (mod Nz)
+    uint32_t tb[3]; // wave: 16 * C * Nz * t' for t' = t, t+1, t-1 (mod Nt)
+    uint32_t xodd;  // lane: x & 1
+    __host__ __device__ __forceinline__ uint32_t at(int32_t d0, int32_t d1, int32_t d2, int32_t d3) const
+    {
+        return xb[shift_slot(d0)] + yb[shift_slot(d1)] + (zb[shift_slot(d2)] + tb[shift_slot(d3)]);
+    }
+    template <class T>
+    __device__ __forceinline__ Quat<T> ld(const Links<T> &U, int mu, int par, uint32_t boff) const
+    {
+        return U.ldb(mu, par, boff);
+    }
+    template <class T>
+    __device__ __forceinline__ void st(const Links<T> &U, int mu, int par, uint32_t boff, const Quat<T> &q) const
+    {
+        U.stb(mu, par, boff, q);
+    }
+    __host__ __device__ __forceinline__ uint32_t site() const
+    {
+        return 2u * ((xb[0] + yb[0] + zb[0] + tb[0]) >> 4) + xodd;
+    }
+};
+
+// Whether a lattice qualifies for ColAddr (host side; the launchers pick it).
+__host__ inline bool col_addressing_ok(const int32_t n[4])
+{
+    const uint64_t cols = (uint64_t)n[0] / 2u * (uint64_t)n[1];
+    const uint64_t half = (uint64_t)n[0] * n[1] * n[2] * n[3] / 2u;
+    return cols % 64u == 0 && half <= (1ull << 28);
+}
+
+// ColAddr of walk index i0 + lane of class `par`, where i0 (a multiple of 64)
+// is the wave's first index; the caller guarantees that the lattice
+// qualifies and that i0 < V/2 (then so are all 64 indices: V/2 is a
+// multiple of C, hence of 64).
+__host__ __device__ __forceinline__ ColAddr col_addr_at(const Geom &g, uint32_t i0, uint32_t lane, int par)
+{
+    const BlockOrder &o = g.ord;
+    const uint32_t j = fdiv(i0, o.div_cols); // column of the walk (wave-uniform)
+    uint32_t z, t;
+    if (o.strip == 0) {
+        t = fdiv(j, g.div_nz);
+        z = j - t * (uint32_t)g.n[2];
+    } else {
+        const uint32_t q = fdiv(j, o.div_w);
+        const uint32_t zz = j - q * o.strip;
+        const uint32_t sidx = fdiv(q, o.div_nt);
+        t = q - sidx * o.div_nt.d;
+        z = sidx * o.strip + zz;
+    }
+    const uint32_t ny = (uint32_t)g.n[1], nz = (uint32_t)g.n[2], nt = (uint32_t)g.n[3];
+    const uint32_t cz = 16u * o.cols, ct = cz * nz;
+    ColAddr a;
+    a.zb[0] = cz * z;
+    a.zb[1] = cz * (z + 1u == nz ? 0u : z + 1u);
+    a.zb[2] = cz * (z == 0u ? nz - 1u : z - 1u);
+    a.tb[0] = ct * t;
+    a.tb[1] = ct * (t + 1u == nt ? 0u : t + 1u);
+    a.tb[2] = ct * (t == 0u ? nt - 1u : t - 1u);
+    const uint32_t off = (i0 - j * o.cols) + lane; // position in the (x,y) plane, in cb units
+    const uint32_t y = fdiv(off, g.div_nxh);
+    const uint32_t xh = off - y * g.nxh;
+    a.xodd = (y + z + t + (uint32_t)par) & 1u;
+    const uint32_t rb = 16u * g.nxh;
+    a.yb[0] = rb * y;
+    a.yb[1] = rb * (y + 1u == ny ? 0u : y + 1u);
+    a.yb[2] = rb * (y == 0u ? ny - 1u : y - 1u);
+    a.xb[0] = 16u * xh;
+    a.xb[1] = a.xodd ? (xh + 1u == g.nxh ? 0u : 16u * (xh + 1u)) : 16u * xh;
+    a.xb[2] = a.xodd ? 16u * xh : (xh == 0u ? 16u * (g.nxh - 1u) : 16u * (xh - 1u));
+    return a;
+}
+
+// The same for walk index i held by a lane of a wave (lane = i & 63): the
+// wave's first index is made scalar so that z, t and the column offsets live
+// in scalar registers.
+__device__ __forceinline__ ColAddr col_addr(const Geom &g, uint32_t i, int par)
+{
+    const uint32_t lane = i & 63u;
+    return col_addr_at(g, __builtin_amdgcn_readfirstlane(i - lane), lane, par);
+}
+
+// ---------------------------------------------------------------------------
+// Staple sum of U_mu(x) (x of parity `par`):
 //   V = sum_{nu != mu} U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
 //                    + U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu)
-// so that the link's local action is -(beta/2) Tr(U_mu(x) V).
+// so that the link's local action is -(beta/2) Tr(U_mu(x) V).  The order of
+// the products and sums is the same for both addressing policies.
 // ---------------------------------------------------------------------------
-template <class T, int MU>
-__device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, const Site &s, uint32_t cb,
-                                          int par)
+template <class T, int MU, class A>
+__device__ __forceinline__ Quat<T> staple(const Links<T> &U, const A &ad, int par)
 {
     const int opp = par ^ 1;
-    const uint32_t cb_xp = cb_shift(g, s.c, MU == 0, MU == 1, MU == 2, MU == 3);
+    const int32_t m0 = (MU == 0), m1 = (MU == 1), m2 = (MU == 2), m3 = (MU == 3);
+    const uint32_t i_xp = ad.at(m0, m1, m2, m3);
+    const uint32_t i_x = ad.at(0, 0, 0, 0);
     Quat<T> V = {0, 0, 0, 0};
 #pragma unroll
     for (int nu = 0; nu < 4; ++nu) {
         if (nu == MU)
             continue;
         const int32_t e0 = (nu == 0), e1 = (nu == 1), e2 = (nu == 2), e3 = (nu == 3);
-        const int32_t m0 = (MU == 0), m1 = (MU == 1), m2 = (MU == 2), m3 = (MU == 3);
-        const uint32_t cb_xpn = cb_shift(g, s.c, e0, e1, e2, e3);
-        const uint32_t cb_xmn = cb_shift(g, s.c, -e0, -e1, -e2, -e3);
-        const uint32_t cb_xpmn = cb_shift(g, s.c, m0 - e0, m1 - e1, m2 - e2, m3 - e3);
+        const uint32_t i_xpn = ad.at(e0, e1, e2, e3);
+        const uint32_t i_xmn = ad.at(-e0, -e1, -e2, -e3);
+        const uint32_t i_xpmn = ad.at(m0 - e0, m1 - e1, m2 - e2, m3 - e3);
         // upper staple
-        const Quat<T> a = U.ld(nu, opp, cb_xp);
-        const Quat<T> b = U.ld(MU, opp, cb_xpn);
-        const Quat<T> c = U.ld(nu, par, cb);
+        const Quat<T> a = ad.ld(U, nu, opp, i_xp);
+        const Quat<T> b = ad.ld(U, MU, opp, i_xpn);
+        const Quat<T> c = ad.ld(U, nu, par, i_x);
         qacc(V, qmul_nd(qmul_nd(a, b), c));
         // lower staple
-        const Quat<T> d = U.ld(nu, par, cb_xpmn);
-        const Quat<T> e = U.ld(MU, opp, cb_xmn);
-        const Quat<T> f = U.ld(nu, opp, cb_xmn);
+        const Quat<T> d = ad.ld(U, nu, par, i_xpmn);
+        const Quat<T> e = ad.ld(U, MU, opp, i_xmn);
+        const Quat<T> f = ad.ld(U, nu, opp, i_xmn);
         qacc(V, qmul(qmul_dd(d, e), f));
     }
     return V;
+}
+
+// The staple from a site's coordinates (any geometry).
+template <class T, int MU>
+__device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, const Site &s, uint32_t cb, int par)
+{
+    CbAddr ad;
+    ad.s = s;
+    ad.cb = cb;
+    ad.g = &g;
+    return staple<T, MU>(U, ad, par);
 }
 
 } // namespace su2

@@ -140,7 +140,7 @@ struct Direction<float> {
 // ballots, no atomics) and retried by as few lanes as there are rejections,
 // so a wave64 no longer idles until its slowest lane accepts.  A link's
 // attempt sequence, and so its result, does not depend on which lane runs it.
-template <class T, int MU>
+template <class T, int MU, bool COL>
 __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, int par, double beta,
                                               uint32_t k0, uint32_t k1, uint32_t c1, uint32_t sweep,
                                               uint32_t *flags, uint32_t b, uint32_t nblocks)
@@ -155,15 +155,24 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     const uint32_t tid = threadIdx.x;
     const uint32_t i = xcd_tile(b, nblocks) * kBlock + tid;
     const bool valid = i < g.half;
-    const uint32_t cb = valid ? walk_cb(i, g.ord) : 0u;
 
-    Site s = {};
+    uint32_t own = 0, site = 0; // own: byte offset (COL) or cb index of the link
     Quat<T> Vh = {1, 0, 0, 0};
     double alpha = 0.0;
     bool need = false;
     if (valid) {
-        s = site_of_cb(g, cb, par);
-        const Quat<T> V = staple<T, MU>(U, g, s, cb, par);
+        Quat<T> V;
+        if constexpr (COL) {
+            const ColAddr ad = col_addr(g, i, par);
+            own = ad.at(0, 0, 0, 0);
+            site = ad.site();
+            V = staple<T, MU>(U, ad, par);
+        } else {
+            own = walk_cb(i, g.ord);
+            const Site s = site_of_cb(g, own, par);
+            site = s.site;
+            V = staple<T, MU>(U, g, s, own, par);
+        }
         const T k = sqrt(V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z);
         if (!isfinite(k)) {
             atomicOr(flags, kFlagNonFinite);
@@ -182,7 +191,7 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     double x0 = 0.0, xlen = 0.0;
     bool ok = false;
     if (need)
-        ok = sampler_attempt<T>(alpha, inv2a, s.site, c1, sweep, 0u, k0, k1, x0, xlen);
+        ok = sampler_attempt<T>(alpha, inv2a, site, c1, sweep, 0u, k0, k1, x0, xlen);
     const bool retry = need && !ok;
 
     // compact the rejected lanes of the block
@@ -191,7 +200,7 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     if (retry) {
         const uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
         s_queue[wave * 64u + rank] = tid;
-        s_site[tid] = s.site;
+        s_site[tid] = site;
         s_alpha[tid] = alpha;
     }
     if (lane == 0)
@@ -227,24 +236,23 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     }
     if (!ok)
         return;
-    const Quat<T> X = Direction<T>::make(x0, xlen, philox(s.site, c1, sweep, 2u, k0, k1));
-    U.st(MU, par, cb, unitize(qmul_nd(X, Vh)));
+    const Quat<T> X = Direction<T>::make(x0, xlen, philox(site, c1, sweep, 2u, k0, k1));
+    const Quat<T> Un = unitize(qmul_nd(X, Vh));
+    if constexpr (COL)
+        U.stb(MU, par, own, Un);
+    else
+        U.st(MU, par, own, Un);
 }
 
 // ---------------------------------------------------------------------------
 // Overrelaxation for one class: U -> Vhat^+ U^+ Vhat^+ = (Vhat U Vhat)^+.
 // ---------------------------------------------------------------------------
-template <class T, int MU>
-__device__ __forceinline__ void overrelax_body(const Links<T> &U, const Geom &g, int par, uint32_t *flags,
-                                               uint32_t b, uint32_t nblocks)
+template <class T, int MU, class A>
+__device__ __forceinline__ void overrelax_link(const Links<T> &U, const A &ad, int par, uint32_t *flags)
 {
-    const uint32_t i = xcd_tile(b, nblocks) * kBlock + threadIdx.x;
-    if (i >= g.half)
-        return;
-    const uint32_t cb = walk_cb(i, g.ord);
-    const Site s = site_of_cb(g, cb, par);
-    const Quat<T> V = staple<T, MU>(U, g, s, cb, par);
-    const Quat<T> u = U.ld(MU, par, cb);
+    const Quat<T> V = staple<T, MU>(U, ad, par);
+    const uint32_t own = ad.at(0, 0, 0, 0);
+    const Quat<T> u = ad.ld(U, MU, par, own);
     const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
     const T k = sqrt(k2);
     if (!isfinite(k)) {
@@ -256,7 +264,25 @@ __device__ __forceinline__ void overrelax_body(const Links<T> &U, const Geom &g,
     const T inv = T(1) / k;
     const Quat<T> Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
     const Quat<T> w = qmul(qmul(Vh, u), Vh);
-    U.st(MU, par, cb, unitize(Quat<T>{w.w, -w.x, -w.y, -w.z}));
+    ad.st(U, MU, par, own, unitize(Quat<T>{w.w, -w.x, -w.y, -w.z}));
+}
+
+template <class T, int MU, bool COL>
+__device__ __forceinline__ void overrelax_body(const Links<T> &U, const Geom &g, int par, uint32_t *flags,
+                                               uint32_t b, uint32_t nblocks)
+{
+    const uint32_t i = xcd_tile(b, nblocks) * kBlock + threadIdx.x;
+    if (i >= g.half)
+        return;
+    if constexpr (COL) {
+        overrelax_link<T, MU>(U, col_addr(g, i, par), par, flags);
+    } else {
+        CbAddr ad;
+        ad.cb = walk_cb(i, g.ord);
+        ad.s = site_of_cb(g, ad.cb, par);
+        ad.g = &g;
+        overrelax_link<T, MU>(U, ad, par, flags);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -267,20 +293,20 @@ __device__ __forceinline__ void overrelax_body(const Links<T> &U, const Geom &g,
 // The heat-bath sweep index is read from device memory when `d_sweep` is
 // given, so a captured graph can be replayed sweep after sweep.
 // ---------------------------------------------------------------------------
-template <class T, int MU>
+template <class T, int MU, bool COL>
 __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, int par, double beta,
                                                            uint32_t k0, uint32_t k1, uint32_t c1,
                                                            uint32_t sweep, const uint32_t *d_sweep,
                                                            uint32_t *flags)
 {
     const uint32_t sw = d_sweep ? *d_sweep : sweep;
-    heatbath_body<T, MU>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x);
+    heatbath_body<T, MU, COL>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x);
 }
 
-template <class T, int MU>
+template <class T, int MU, bool COL>
 __global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags)
 {
-    overrelax_body<T, MU>(U, g, par, flags, blockIdx.x, gridDim.x);
+    overrelax_body<T, MU, COL>(U, g, par, flags, blockIdx.x, gridDim.x);
 }
 
 __device__ __forceinline__ const BatchEntry &find_entry(const BatchEntry *tab, int count)
@@ -302,7 +328,11 @@ __global__ __launch_bounds__(kBlock) void heatbath_batch_kernel(const BatchEntry
     U.half = e.g.half;
     const uint32_t sw = d_sweep ? *d_sweep : sweep;
     const uint32_t c1 = (uint32_t)MU + 4u * 1u + e.lid16;
-    heatbath_body<T, MU>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, blockIdx.x - e.block0, e.nblocks);
+    if (e.col)
+        heatbath_body<T, MU, true>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, blockIdx.x - e.block0, e.nblocks);
+    else
+        heatbath_body<T, MU, false>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, blockIdx.x - e.block0,
+                                    e.nblocks);
 }
 
 template <class T, int MU>
@@ -312,7 +342,10 @@ __global__ __launch_bounds__(kBlock) void overrelax_batch_kernel(const BatchEntr
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(e.links);
     U.half = e.g.half;
-    overrelax_body<T, MU>(U, e.g, par, e.flags, blockIdx.x - e.block0, e.nblocks);
+    if (e.col)
+        overrelax_body<T, MU, true>(U, e.g, par, e.flags, blockIdx.x - e.block0, e.nblocks);
+    else
+        overrelax_body<T, MU, false>(U, e.g, par, e.flags, blockIdx.x - e.block0, e.nblocks);
 }
 
 __global__ void sweep_advance_kernel(uint32_t *d_sweep)
@@ -523,50 +556,6 @@ __global__ void copy_flags_kernel(const uint32_t *flags, uint32_t *dst)
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-int default_strip(const int32_t n[4])
-{
-    const uint32_t nz = (uint32_t)n[2];
-    uint32_t w = nz / 8u > 0 ? nz / 8u : 1u;
-    while (nz % w)
-        --w;
-    return (int)w;
-}
-
-// Walk of a class: tile > 0 is the strip width (it divides Nz; the caller
-// checked), tile == 0 the default (Nz/8 rounded down to a divisor of Nz, so
-// that each of the 8 XCDs takes one strip), tile < 0 plain cb order.
-static BlockOrder make_block_order(const int32_t n[4], int tile)
-{
-    BlockOrder o = {};
-    o.cols = (uint32_t)n[0] / 2u * (uint32_t)n[1];
-    o.nz = (uint32_t)n[2];
-    const int w = tile == 0 ? default_strip(n) : tile;
-    if (w <= 0)
-        return o;
-    o.strip = (uint32_t)w;
-    o.div_cols = make_fastdiv(o.cols);
-    o.div_w = make_fastdiv(o.strip);
-    o.div_nt = make_fastdiv((uint32_t)n[3]);
-    return o;
-}
-
-static Geom make_geom(const int32_t n[4], int tile)
-{
-    Geom g;
-    for (int d = 0; d < 4; ++d)
-        g.n[d] = n[d];
-    g.nxh = (uint32_t)n[0] / 2u;
-    const uint64_t vol = (uint64_t)n[0] * n[1] * n[2] * n[3];
-    g.half = (uint32_t)(vol / 2);
-    g.vs = (uint32_t)((uint64_t)n[0] * n[1] * n[2]);
-    g.div_nx = make_fastdiv((uint32_t)n[0]);
-    g.div_nxh = make_fastdiv(g.nxh);
-    g.div_ny = make_fastdiv((uint32_t)n[1]);
-    g.div_nz = make_fastdiv((uint32_t)n[2]);
-    g.ord = make_block_order(n, tile);
-    return g;
-}
-
 template <class T>
 static Links<T> links_of(const LaunchArgs &a)
 {
@@ -599,9 +588,24 @@ void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_
     e.flags = a.flags;
     e.beta = beta;
     e.lid16 = 16u * (uint32_t)a.lattice_id;
+    e.col = col_addressing_ok(a.n) ? 1u : 0u;
     e.block0 = block0;
     e.nblocks = nblocks;
     std::memcpy(dst, &e, sizeof e);
+}
+
+template <class T, bool COL>
+static void launch_hb_mode(const Links<T> &U, const Geom &g, int mu, int par, double beta, uint32_t k0,
+                           uint32_t k1, uint32_t c1, uint32_t sweep, const uint32_t *d_sweep, uint32_t *flags,
+                           hipStream_t st)
+{
+    const dim3 grid(blocks_for(g.half)), block(kBlock);
+    switch (mu) {
+    case 0: heatbath_kernel<T, 0, COL><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags); break;
+    case 1: heatbath_kernel<T, 1, COL><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags); break;
+    case 2: heatbath_kernel<T, 2, COL><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags); break;
+    default: heatbath_kernel<T, 3, COL><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags); break;
+    }
 }
 
 template <class T>
@@ -611,12 +615,21 @@ static void launch_hb(const LaunchArgs &a, const Geom &g, int mu, int par, doubl
     const Links<T> U = links_of<T>(a);
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = (uint32_t)mu + 4u * 1u + 16u * (uint32_t)a.lattice_id;
+    if (col_addressing_ok(a.n))
+        launch_hb_mode<T, true>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, st);
+    else
+        launch_hb_mode<T, false>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, st);
+}
+
+template <class T, bool COL>
+static void launch_or_mode(const Links<T> &U, const Geom &g, int mu, int par, uint32_t *flags, hipStream_t st)
+{
     const dim3 grid(blocks_for(g.half)), block(kBlock);
     switch (mu) {
-    case 0: heatbath_kernel<T, 0><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, a.flags); break;
-    case 1: heatbath_kernel<T, 1><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, a.flags); break;
-    case 2: heatbath_kernel<T, 2><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, a.flags); break;
-    default: heatbath_kernel<T, 3><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, a.flags); break;
+    case 0: overrelax_kernel<T, 0, COL><<<grid, block, 0, st>>>(U, g, par, flags); break;
+    case 1: overrelax_kernel<T, 1, COL><<<grid, block, 0, st>>>(U, g, par, flags); break;
+    case 2: overrelax_kernel<T, 2, COL><<<grid, block, 0, st>>>(U, g, par, flags); break;
+    default: overrelax_kernel<T, 3, COL><<<grid, block, 0, st>>>(U, g, par, flags); break;
     }
 }
 
@@ -624,13 +637,10 @@ template <class T>
 static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, hipStream_t st)
 {
     const Links<T> U = links_of<T>(a);
-    const dim3 grid(blocks_for(g.half)), block(kBlock);
-    switch (mu) {
-    case 0: overrelax_kernel<T, 0><<<grid, block, 0, st>>>(U, g, par, a.flags); break;
-    case 1: overrelax_kernel<T, 1><<<grid, block, 0, st>>>(U, g, par, a.flags); break;
-    case 2: overrelax_kernel<T, 2><<<grid, block, 0, st>>>(U, g, par, a.flags); break;
-    default: overrelax_kernel<T, 3><<<grid, block, 0, st>>>(U, g, par, a.flags); break;
-    }
+    if (col_addressing_ok(a.n))
+        launch_or_mode<T, true>(U, g, mu, par, a.flags, st);
+    else
+        launch_or_mode<T, false>(U, g, mu, par, a.flags, st);
 }
 
 void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st)

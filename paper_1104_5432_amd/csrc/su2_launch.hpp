@@ -31,7 +31,6 @@ struct LaunchArgs {
 
 WorkLayout work_layout(const int32_t n[4]);
 
-int default_strip(const int32_t n[4]);
 uint32_t class_blocks(const LaunchArgs &a);
 uint64_t batch_entry_bytes();
 void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_t nblocks, void *dst);

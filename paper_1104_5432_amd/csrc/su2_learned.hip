@@ -717,17 +717,7 @@ __global__ __launch_bounds__(256) void adam_kernel(float *p, const float *grad, 
 // ---------------------------------------------------------------------------
 static Geom geom_of(const LaunchArgs &a)
 {
-    Geom g = {};
-    for (int d = 0; d < 4; ++d)
-        g.n[d] = a.n[d];
-    g.nxh = (uint32_t)a.n[0] / 2u;
-    g.half = (uint32_t)(a.volume / 2);
-    g.vs = (uint32_t)((uint64_t)a.n[0] * a.n[1] * a.n[2]);
-    g.div_nx = make_fastdiv((uint32_t)a.n[0]);
-    g.div_nxh = make_fastdiv(g.nxh);
-    g.div_ny = make_fastdiv((uint32_t)a.n[1]);
-    g.div_nz = make_fastdiv((uint32_t)a.n[2]);
-    return g;   // plain walk; the learned kernels index sites directly
+    return make_geom(a.n, -1); // plain walk; the learned kernels index sites directly
 }
 
 template <class T>
