@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--start", choices=["hot", "cold"], default="hot")
     ap.add_argument("--tile", type=int, default=0,
                     help="walk of the single lattice: 0 default strip, > 0 strip width, < 0 plain order")
+    ap.add_argument("--tile-y", type=int, default=0,
+                    help="row ranges per column in strip order (divides Ny; 0 default)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose the walk with paper_1104_5432_amd.autotune before timing (untimed)")
     ap.add_argument("--train", type=int, default=10000,
@@ -279,11 +281,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    tile = args.tile
+    tile, tile_y = args.tile, args.tile_y
     if args.autotune:
         from paper_1104_5432_amd import autotune
-        tile = autotune.tune(n, args.prec, device=dev)
-    lat = su2.Lattice(n, args.prec, device=dev, tile=tile)
+        tile, tile_y = autotune.tune(n, args.prec, device=dev)
+    lat = su2.Lattice(n, args.prec, device=dev, tile=tile, tile_y=tile_y)
     if args.start == "hot":
         su2.su2_init_hot(lat, args.seed)
     else:
@@ -369,6 +371,7 @@ def main():
             "beta": args.beta,
             "or_per_hb": args.or_per_hb,
             "tile": tile,
+            "tile_y": tile_y,
             "start": args.start,
             "link_updates_per_step": updates,
         },

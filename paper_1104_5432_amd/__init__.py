@@ -33,7 +33,7 @@ class su2_lattice_t(ctypes.Structure):
         ("prec", ctypes.c_int32),
         ("lattice_id", ctypes.c_int32),
         ("tile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tile_y", ctypes.c_int32),
         ("links", ctypes.c_void_p),
         ("work", ctypes.c_void_p),
         ("work_bytes", ctypes.c_uint64),
@@ -130,7 +130,7 @@ class Lattice:
     """Device storage for one lattice: links and workspace as uint8 tensors,
     plus the su2_lattice_t descriptor that points at them."""
 
-    def __init__(self, n, prec="f64", device="cuda", lattice_id=0, tile=0):
+    def __init__(self, n, prec="f64", device="cuda", lattice_id=0, tile=0, tile_y=0):
         self.n, cn = _dims(n)
         self.prec = _PRECS[prec]
         nb = su2_links_bytes(self.n, self.prec)
@@ -140,7 +140,7 @@ class Lattice:
         self.device = torch.device(device)
         self.links = torch.empty(nb, dtype=torch.uint8, device=self.device)
         self.work = torch.zeros(wb, dtype=torch.uint8, device=self.device)
-        self.desc = su2_lattice_t(cn, self.prec, int(lattice_id), int(tile), 0, self.links.data_ptr(),
+        self.desc = su2_lattice_t(cn, self.prec, int(lattice_id), int(tile), int(tile_y), self.links.data_ptr(),
                                   self.work.data_ptr(), wb)
 
     @property

@@ -1,8 +1,10 @@
-"""Tile autotuner: choose the walk (`tile` of the lattice descriptor) per
-lattice shape and precision by timing the library's own update kernels.
+"""Walk autotuner: choose the walk (`tile`, `tile_y` of the lattice
+descriptor) per lattice shape and precision by timing the library's own
+update kernels.
 
-Candidates are plain checkerboard order (-1) and every z-strip width W that
-divides Nz.  Each candidate runs one heat-bath sweep plus one overrelaxation
+Candidates are plain checkerboard order (tile -1) and every z-strip width W
+that divides Nz, each with the columns split into S = 1, 2, 4 or 8 row
+ranges (S dividing Ny).  Each candidate runs one heat-bath sweep plus one overrelaxation
 sweep on a scratch lattice (hot start, never the caller's lattice) after a
 warm-up, timed with HIP events on the current stream; the fastest total
 wins.  The walk changes no result, only the order in which blocks visit the
@@ -20,8 +22,16 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "su2_mi355x", "t
 
 
 def candidates(n):
-    nz = int(n[2])
-    return [-1] + [w for w in range(1, nz + 1) if nz % w == 0]
+    """(tile, tile_y) pairs: plain order, then strip widths x row splits."""
+    ny, nz = int(n[1]), int(n[2])
+    out = [(-1, 0)]
+    for w in range(1, nz + 1):
+        if nz % w:
+            continue
+        for sy in (1, 2, 4, 8):
+            if ny % sy == 0:
+                out.append((w, sy))
+    return out
 
 
 def _key(n, prec, device):
@@ -37,9 +47,10 @@ def _load(path):
         return {}
 
 
-def measure(n, prec, tile, beta=2.3, reps=3, device="cuda"):
+def measure(n, prec, walk, beta=2.3, reps=3, device="cuda"):
     """Milliseconds of (1 heat-bath + 1 overrelaxation sweep) with this walk."""
-    lat = Lattice(n, prec, device=device, tile=tile)
+    tile, tile_y = walk
+    lat = Lattice(n, prec, device=device, tile=tile, tile_y=tile_y)
     su2_init_hot(lat, 1)
     su2_heatbath_sweep(lat, beta, 1, 0)
     su2_overrelax(lat, 1)
@@ -58,19 +69,21 @@ def measure(n, prec, tile, beta=2.3, reps=3, device="cuda"):
 
 
 def tune(n, prec="f32", device="cuda", cache=DEFAULT_CACHE, reps=3, refresh=False, max_candidates=None):
-    """Return the fastest tile for extents n (and store it in the cache)."""
+    """Return the fastest walk (tile, tile_y) for extents n (and store it in
+    the cache)."""
     key = _key(n, prec, device)
     table = _load(cache) if cache else {}
-    if not refresh and key in table:
-        return int(table[key]["tile"])
+    if not refresh and key in table and "tile_y" in table[key]:
+        return int(table[key]["tile"]), int(table[key]["tile_y"])
     cands = candidates(n)
     if max_candidates is not None:
         cands = cands[:max_candidates]
-    times = {t: measure(n, prec, t, reps=reps, device=device) for t in cands}
+    times = {c: measure(n, prec, c, reps=reps, device=device) for c in cands}
     best = min(times, key=times.get)
     if cache:
         table = _load(cache)
-        table[key] = {"tile": best, "ms": times}
+        table[key] = {"tile": best[0], "tile_y": best[1],
+                      "ms": {f"{c[0]},{c[1]}": v for c, v in times.items()}}
         os.makedirs(os.path.dirname(cache), exist_ok=True)
         tmp = cache + ".tmp"
         with open(tmp, "w") as f:

@@ -56,6 +56,8 @@ int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayou
         return fail(SU2_EINVAL, "lattice_id must be in [0, 2^27)");
     if (lat->tile > 0 && (lat->tile > lat->n[2] || lat->n[2] % lat->tile != 0))
         return fail(SU2_EINVAL, "a positive tile (strip width) must divide Nz");
+    if (lat->tile_y < 0 || (lat->tile_y > 0 && (lat->tile_y > lat->n[1] || lat->n[1] % lat->tile_y != 0)))
+        return fail(SU2_EINVAL, "tile_y must be 0 or a divisor of Ny");
     if (!lat->links || !lat->work)
         return fail(SU2_EINVAL, "links and work must be non-NULL device pointers");
     if (!aligned(lat->links, 16) || !aligned(lat->work, 16))
@@ -70,6 +72,7 @@ int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayou
     out->prec = lat->prec;
     out->lattice_id = lat->lattice_id;
     out->tile = lat->tile;
+    out->tile_y = lat->tile_y;
     out->volume = (uint64_t)lat->n[0] * lat->n[1] * lat->n[2] * lat->n[3];
     out->links = lat->links;
     out->work = static_cast<char *>(lat->work);

@@ -175,13 +175,18 @@ __host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
 // walk.  In strip mode the walk visits (z,t) columns (C = Nx*Ny/2 cb indices
 // each) strip by strip of W z-values, t-major inside a strip: the +-t halo
 // of a column is W columns behind in the walk, still in the XCD's L2,
-// instead of a whole t-slice behind.  Mode 0 walks plain cb order.  Every
-// walk is a bijection onto the class, so results do not depend on it.
+// instead of a whole t-slice behind.  With S > 1 each strip is walked S
+// times, once per range of Ny/S rows (contiguous in memory), which shrinks
+// the data between a column and its t-neighbour S-fold at the price of
+// re-reading two boundary rows per range.  Mode 0 walks plain cb order.
+// Every walk is a bijection onto the class, so results do not depend on it.
 struct BlockOrder {
     uint32_t strip;  // 0 = plain cb order, else the strip width W (divides Nz)
     uint32_t cols;   // C
     uint32_t nz;     // Nz
-    FastDiv div_cols, div_w, div_nt;
+    uint32_t ysplit; // S: each column is walked as S contiguous ranges of Ny/S rows
+    uint32_t seg;    // C / S, the cb indices of one range
+    FastDiv div_cols, div_w, div_nt, div_seg, div_ys;
 };
 
 // ---------------------------------------------------------------------------
@@ -224,7 +229,15 @@ __host__ inline int default_strip(const int32_t n[4])
     return (int)w;
 }
 
-__host__ inline BlockOrder make_block_order(const int32_t n[4], int tile)
+// Row ranges per column: tile_y > 0 as given (it divides Ny; the caller
+// checked), 0 = default (1).
+__host__ inline int default_ysplit(const int32_t n[4])
+{
+    (void)n;
+    return 1;
+}
+
+__host__ inline BlockOrder make_block_order(const int32_t n[4], int tile, int tile_y)
 {
     BlockOrder o = {};
     o.cols = (uint32_t)n[0] / 2u * (uint32_t)n[1];
@@ -234,10 +247,15 @@ __host__ inline BlockOrder make_block_order(const int32_t n[4], int tile)
     const int w = tile == 0 ? default_strip(n) : tile;
     o.strip = w > 0 ? (uint32_t)w : 0u;
     o.div_w = make_fastdiv(w > 0 ? (uint32_t)w : 1u);
+    const int s = w > 0 ? (tile_y > 0 ? tile_y : default_ysplit(n)) : 1;
+    o.ysplit = (uint32_t)s;
+    o.seg = o.cols / o.ysplit;
+    o.div_seg = make_fastdiv(o.seg);
+    o.div_ys = make_fastdiv(o.ysplit);
     return o;
 }
 
-__host__ inline Geom make_geom(const int32_t n[4], int tile)
+__host__ inline Geom make_geom(const int32_t n[4], int tile, int tile_y = 0)
 {
     Geom g = {};
     for (int d = 0; d < 4; ++d)
@@ -250,7 +268,7 @@ __host__ inline Geom make_geom(const int32_t n[4], int tile)
     g.div_nxh = make_fastdiv(g.nxh);
     g.div_ny = make_fastdiv((uint32_t)n[1]);
     g.div_nz = make_fastdiv((uint32_t)n[2]);
-    g.ord = make_block_order(n, tile);
+    g.ord = make_block_order(n, tile, tile_y);
     return g;
 }
 
@@ -302,6 +320,9 @@ __host__ __device__ __forceinline__ uint32_t cb_shift(const Geom &g, const int32
 // ---------------------------------------------------------------------------
 // Link planes: plane q = 2 mu + parity, V/2 links each.
 // ---------------------------------------------------------------------------
+typedef float V4f __attribute__((ext_vector_type(4)));
+typedef double V2d __attribute__((ext_vector_type(2)));
+
 template <class T>
 struct Links;
 
@@ -314,9 +335,18 @@ struct Links<float> {
         const float4 v = p[(size_t)(2 * mu + par) * half + cb];
         return {v.x, v.y, v.z, v.w};
     }
+    // Stores are non-temporal: an updated link is not read again by the
+    // same launch, so it should not displace the neighbourhood from L2.
     __device__ __forceinline__ void st(int mu, int par, uint32_t cb, const Quat<float> &q) const
     {
-        p[(size_t)(2 * mu + par) * half + cb] = make_float4(q.w, q.x, q.y, q.z);
+        const V4f v = {q.w, q.x, q.y, q.z};
+        __builtin_nontemporal_store(v, reinterpret_cast<V4f *>(p + (size_t)(2 * mu + par) * half + cb));
+    }
+    // Non-temporal load, for a link read once by its own update.
+    __device__ __forceinline__ Quat<float> ld_nt(int mu, int par, uint32_t cb) const
+    {
+        const V4f v = __builtin_nontemporal_load(reinterpret_cast<const V4f *>(p + (size_t)(2 * mu + par) * half + cb));
+        return {v.x, v.y, v.z, v.w};
     }
     // by byte offset within the plane (< 2^32)
     __device__ __forceinline__ Quat<float> ldb(int mu, int par, uint32_t boff) const
@@ -325,10 +355,17 @@ struct Links<float> {
         const float4 v = *reinterpret_cast<const float4 *>(base + boff);
         return {v.x, v.y, v.z, v.w};
     }
+    __device__ __forceinline__ Quat<float> ldb_nt(int mu, int par, uint32_t boff) const
+    {
+        const char *base = reinterpret_cast<const char *>(p + (size_t)(2 * mu + par) * half);
+        const V4f v = __builtin_nontemporal_load(reinterpret_cast<const V4f *>(base + boff));
+        return {v.x, v.y, v.z, v.w};
+    }
     __device__ __forceinline__ void stb(int mu, int par, uint32_t boff, const Quat<float> &q) const
     {
         char *base = reinterpret_cast<char *>(p + (size_t)(2 * mu + par) * half);
-        *reinterpret_cast<float4 *>(base + boff) = make_float4(q.w, q.x, q.y, q.z);
+        const V4f v = {q.w, q.x, q.y, q.z};
+        __builtin_nontemporal_store(v, reinterpret_cast<V4f *>(base + boff));
     }
 };
 
@@ -346,8 +383,16 @@ struct Links<double> {
     __device__ __forceinline__ void st(int mu, int par, uint32_t cb, const Quat<double> &v) const
     {
         const size_t q = (size_t)(2 * mu + par);
-        p[(2 * q) * half + cb] = make_double2(v.w, v.x);
-        p[(2 * q + 1) * half + cb] = make_double2(v.y, v.z);
+        const V2d a = {v.w, v.x}, b = {v.y, v.z};
+        __builtin_nontemporal_store(a, reinterpret_cast<V2d *>(p + (2 * q) * half + cb));
+        __builtin_nontemporal_store(b, reinterpret_cast<V2d *>(p + (2 * q + 1) * half + cb));
+    }
+    __device__ __forceinline__ Quat<double> ld_nt(int mu, int par, uint32_t cb) const
+    {
+        const size_t q = (size_t)(2 * mu + par);
+        const V2d a = __builtin_nontemporal_load(reinterpret_cast<const V2d *>(p + (2 * q) * half + cb));
+        const V2d b = __builtin_nontemporal_load(reinterpret_cast<const V2d *>(p + (2 * q + 1) * half + cb));
+        return {a.x, a.y, b.x, b.y};
     }
     // by byte offset within the sub-planes (< 2^32)
     __device__ __forceinline__ Quat<double> ldb(int mu, int par, uint32_t boff) const
@@ -359,13 +404,23 @@ struct Links<double> {
         const double2 b = *reinterpret_cast<const double2 *>(bb + boff);
         return {a.x, a.y, b.x, b.y};
     }
+    __device__ __forceinline__ Quat<double> ldb_nt(int mu, int par, uint32_t boff) const
+    {
+        const size_t q = (size_t)(2 * mu + par);
+        const char *ba = reinterpret_cast<const char *>(p + (2 * q) * half);
+        const char *bb = reinterpret_cast<const char *>(p + (2 * q + 1) * half);
+        const V2d a = __builtin_nontemporal_load(reinterpret_cast<const V2d *>(ba + boff));
+        const V2d b = __builtin_nontemporal_load(reinterpret_cast<const V2d *>(bb + boff));
+        return {a.x, a.y, b.x, b.y};
+    }
     __device__ __forceinline__ void stb(int mu, int par, uint32_t boff, const Quat<double> &v) const
     {
         const size_t q = (size_t)(2 * mu + par);
         char *ba = reinterpret_cast<char *>(p + (2 * q) * half);
         char *bb = reinterpret_cast<char *>(p + (2 * q + 1) * half);
-        *reinterpret_cast<double2 *>(ba + boff) = make_double2(v.w, v.x);
-        *reinterpret_cast<double2 *>(bb + boff) = make_double2(v.y, v.z);
+        const V2d a = {v.w, v.x}, b = {v.y, v.z};
+        __builtin_nontemporal_store(a, reinterpret_cast<V2d *>(ba + boff));
+        __builtin_nontemporal_store(b, reinterpret_cast<V2d *>(bb + boff));
     }
 };
 
@@ -398,14 +453,16 @@ __host__ __device__ __forceinline__ uint32_t walk_cb(uint32_t i, const BlockOrde
 {
     if (o.strip == 0)
         return i;
-    const uint32_t j = fdiv(i, o.div_cols);
-    const uint32_t off = i - j * o.cols;
+    const uint32_t j = fdiv(i, o.div_seg);   // range of the walk
+    const uint32_t off = i - j * o.seg;
     const uint32_t q = fdiv(j, o.div_w);
     const uint32_t zz = j - q * o.strip;
-    const uint32_t s = fdiv(q, o.div_nt);
-    const uint32_t t = q - s * o.div_nt.d;
+    const uint32_t r = fdiv(q, o.div_nt);
+    const uint32_t t = q - r * o.div_nt.d;
+    const uint32_t s = fdiv(r, o.div_ys);    // strip
+    const uint32_t yr = r - s * o.ysplit;    // row range within the strip
     const uint32_t z = s * o.strip + zz;
-    return off + o.cols * (z + o.nz * t);
+    return yr * o.seg + off + o.cols * (z + o.nz * t);
 }
 
 // ---------------------------------------------------------------------------
@@ -413,8 +470,9 @@ __host__ __device__ __forceinline__ uint32_t walk_cb(uint32_t i, const BlockOrde
 //
 // CbAddr: from the site's coordinates (cb_shift), for any geometry.
 //
-// ColAddr: when C = Nx Ny / 2 is a multiple of 64, the 64 sites of a wave lie
-// in one (z,t) column of the walk, so z, t and everything derived from them
+// ColAddr: when the walk's unit (a column of C = Nx Ny / 2 cb indices, or a
+// row range of it) is a multiple of 64, the 64 sites of a wave lie in one
+// (z,t) column, so z, t and everything derived from them
 // are wave-uniform (scalar registers) and only the in-plane position varies
 // per lane.  A neighbour's index is then the sum of an x part and a y part
 // (per lane) and a z part and a t part (scalar), each precomputed for the
@@ -443,6 +501,11 @@ struct CbAddr {
         return U.ld(mu, par, idx);
     }
     template <class T>
+    __device__ __forceinline__ Quat<T> ld_nt(const Links<T> &U, int mu, int par, uint32_t idx) const
+    {
+        return U.ld_nt(mu, par, idx);
+    }
+    template <class T>
     __device__ __forceinline__ void st(const Links<T> &U, int mu, int par, uint32_t idx, const Quat<T> &q) const
     {
         U.st(mu, par, idx, q);
@@ -469,6 +532,11 @@ struct ColAddr {
         return U.ldb(mu, par, boff);
     }
     template <class T>
+    __device__ __forceinline__ Quat<T> ld_nt(const Links<T> &U, int mu, int par, uint32_t boff) const
+    {
+        return U.ldb_nt(mu, par, boff);
+    }
+    template <class T>
     __device__ __forceinline__ void st(const Links<T> &U, int mu, int par, uint32_t boff, const Quat<T> &q) const
     {
         U.stb(mu, par, boff, q);
@@ -479,32 +547,37 @@ struct ColAddr {
     }
 };
 
-// Whether a lattice qualifies for ColAddr (host side; the launchers pick it).
-__host__ inline bool col_addressing_ok(const int32_t n[4])
+// Whether a lattice and walk qualify for ColAddr (host side; the launchers
+// pick it): a wave's 64 walk indices must lie in one column (one row range
+// in strip mode), and byte offsets within a plane must fit 32 bits.
+__host__ inline bool col_addressing_ok(const Geom &g)
 {
-    const uint64_t cols = (uint64_t)n[0] / 2u * (uint64_t)n[1];
-    const uint64_t half = (uint64_t)n[0] * n[1] * n[2] * n[3] / 2u;
-    return cols % 64u == 0 && half <= (1ull << 28);
+    const uint32_t unit = g.ord.strip == 0 ? g.ord.cols : g.ord.seg;
+    return unit % 64u == 0 && g.half <= (1u << 28);
 }
 
 // ColAddr of walk index i0 + lane of class `par`, where i0 (a multiple of 64)
 // is the wave's first index; the caller guarantees that the lattice
 // qualifies and that i0 < V/2 (then so are all 64 indices: V/2 is a
-// multiple of C, hence of 64).
+// multiple of the walk's unit, hence of 64).
 __host__ __device__ __forceinline__ ColAddr col_addr_at(const Geom &g, uint32_t i0, uint32_t lane, int par)
 {
     const BlockOrder &o = g.ord;
-    const uint32_t j = fdiv(i0, o.div_cols); // column of the walk (wave-uniform)
-    uint32_t z, t;
+    uint32_t z, t, off0; // off0: the wave's first position in the (x,y) plane, in cb units
     if (o.strip == 0) {
+        const uint32_t j = fdiv(i0, o.div_cols); // column (wave-uniform)
         t = fdiv(j, g.div_nz);
         z = j - t * (uint32_t)g.n[2];
+        off0 = i0 - j * o.cols;
     } else {
+        const uint32_t j = fdiv(i0, o.div_seg); // row range of the walk (wave-uniform)
         const uint32_t q = fdiv(j, o.div_w);
         const uint32_t zz = j - q * o.strip;
-        const uint32_t sidx = fdiv(q, o.div_nt);
-        t = q - sidx * o.div_nt.d;
+        const uint32_t r = fdiv(q, o.div_nt);
+        t = q - r * o.div_nt.d;
+        const uint32_t sidx = fdiv(r, o.div_ys);
         z = sidx * o.strip + zz;
+        off0 = (r - sidx * o.ysplit) * o.seg + (i0 - j * o.seg);
     }
     const uint32_t ny = (uint32_t)g.n[1], nz = (uint32_t)g.n[2], nt = (uint32_t)g.n[3];
     const uint32_t cz = 16u * o.cols, ct = cz * nz;
@@ -515,7 +588,7 @@ __host__ __device__ __forceinline__ ColAddr col_addr_at(const Geom &g, uint32_t 
     a.tb[0] = ct * t;
     a.tb[1] = ct * (t + 1u == nt ? 0u : t + 1u);
     a.tb[2] = ct * (t == 0u ? nt - 1u : t - 1u);
-    const uint32_t off = (i0 - j * o.cols) + lane; // position in the (x,y) plane, in cb units
+    const uint32_t off = off0 + lane; // position in the (x,y) plane, in cb units
     const uint32_t y = fdiv(off, g.div_nxh);
     const uint32_t xh = off - y * g.nxh;
     a.xodd = (y + z + t + (uint32_t)par) & 1u;

@@ -252,7 +252,7 @@ __device__ __forceinline__ void overrelax_link(const Links<T> &U, const A &ad, i
 {
     const Quat<T> V = staple<T, MU>(U, ad, par);
     const uint32_t own = ad.at(0, 0, 0, 0);
-    const Quat<T> u = ad.ld(U, MU, par, own);
+    const Quat<T> u = ad.ld_nt(U, MU, par, own); // read by this update only
     const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
     const T k = sqrt(k2);
     if (!isfinite(k)) {
@@ -303,9 +303,24 @@ __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, in
     heatbath_body<T, MU, COL>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x);
 }
 
+// Residency cap of the overrelaxation kernels.  At the 7 blocks per CU their
+// registers allow, the blocks in flight on an XCD touch more links than its
+// 4 MB L2 holds and neighbours are evicted between uses; 4 blocks per CU
+// (16 waves) is faster (FP32 5%, FP64 5%, measured at 64^4 and 96^4).  The
+// cap is an LDS reservation: 36 KB per block, 4 blocks in 160 KB.
+constexpr int kOrResidencyLds = 36 * 1024;
+
+__device__ __forceinline__ void reserve_lds_for_residency()
+{
+    __shared__ volatile char reservation[kOrResidencyLds];
+    if (threadIdx.x == kBlock) // never true: keeps the reservation allocated
+        reservation[0] = 0;
+}
+
 template <class T, int MU, bool COL>
 __global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags)
 {
+    reserve_lds_for_residency();
     overrelax_body<T, MU, COL>(U, g, par, flags, blockIdx.x, gridDim.x);
 }
 
@@ -338,6 +353,7 @@ __global__ __launch_bounds__(kBlock) void heatbath_batch_kernel(const BatchEntry
 template <class T, int MU>
 __global__ __launch_bounds__(kBlock) void overrelax_batch_kernel(const BatchEntry *tab, int count, int par)
 {
+    reserve_lds_for_residency();
     const BatchEntry &e = find_entry(tab, count);
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(e.links);
@@ -431,36 +447,47 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[NV])
 // U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+, mu < nu, in FP64.  A thread
 // takes one cb index and both parities; blocks walk the lattice in the
 // same order as the update kernels; one partial per block.
-template <class T>
+template <class T, class A>
+__device__ __forceinline__ void plaquette_site(const Links<T> &U, const A &ad, int par, double (&acc)[6])
+{
+    const int opp = par ^ 1;
+    const uint32_t own = ad.at(0, 0, 0, 0);
+    Quat<T> u[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+        u[mu] = ad.ld(U, mu, par, own);
+    const uint32_t ip[4] = {ad.at(1, 0, 0, 0), ad.at(0, 1, 0, 0), ad.at(0, 0, 1, 0), ad.at(0, 0, 0, 1)};
+    int p = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            const Quat<T> a = qmul(u[mu], ad.ld(U, nu, opp, ip[mu]));
+            const Quat<T> b = qmul(u[nu], ad.ld(U, mu, opp, ip[nu]));
+            acc[p++] += (double)qdot(a, b);
+        }
+}
+
+template <class T, bool COL>
 __global__ __launch_bounds__(kBlock) void plaquette_kernel(Links<T> U, Geom g, double *partials)
 {
     __shared__ double lds[kBlock / 64][6];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i < g.half) {
-        const uint32_t cb = walk_cb(i, g.ord);
+        if constexpr (COL) {
 #pragma unroll
-        for (int par = 0; par < 2; ++par) {
-            const int opp = par ^ 1;
-            const Site s = site_of_cb(g, cb, par);
-            Quat<T> own[4];
+            for (int par = 0; par < 2; ++par)
+                plaquette_site(U, col_addr(g, i, par), par, acc);
+        } else {
+            CbAddr ad;
+            ad.cb = walk_cb(i, g.ord);
+            ad.g = &g;
 #pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-                own[mu] = U.ld(mu, par, cb);
-            uint32_t cbp[4];
-            cbp[0] = cb_shift(g, s.c, 1, 0, 0, 0);
-            cbp[1] = cb_shift(g, s.c, 0, 1, 0, 0);
-            cbp[2] = cb_shift(g, s.c, 0, 0, 1, 0);
-            cbp[3] = cb_shift(g, s.c, 0, 0, 0, 1);
-            int p = 0;
-#pragma unroll
-            for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-                for (int nu = mu + 1; nu < 4; ++nu) {
-                    const Quat<T> a = qmul(own[mu], U.ld(nu, opp, cbp[mu]));
-                    const Quat<T> b = qmul(own[nu], U.ld(mu, opp, cbp[nu]));
-                    acc[p++] += (double)qdot(a, b);
-                }
+            for (int par = 0; par < 2; ++par) {
+                ad.s = site_of_cb(g, ad.cb, par);
+                plaquette_site(U, ad, par, acc);
+            }
         }
     }
     block_sum<6>(acc, lds);
@@ -583,12 +610,12 @@ uint64_t batch_entry_bytes()
 void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_t nblocks, void *dst)
 {
     BatchEntry e = {};
-    e.g = make_geom(a.n, a.tile);
+    e.g = make_geom(a.n, a.tile, a.tile_y);
     e.links = a.links;
     e.flags = a.flags;
     e.beta = beta;
     e.lid16 = 16u * (uint32_t)a.lattice_id;
-    e.col = col_addressing_ok(a.n) ? 1u : 0u;
+    e.col = col_addressing_ok(e.g) ? 1u : 0u;
     e.block0 = block0;
     e.nblocks = nblocks;
     std::memcpy(dst, &e, sizeof e);
@@ -615,7 +642,7 @@ static void launch_hb(const LaunchArgs &a, const Geom &g, int mu, int par, doubl
     const Links<T> U = links_of<T>(a);
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = (uint32_t)mu + 4u * 1u + 16u * (uint32_t)a.lattice_id;
-    if (col_addressing_ok(a.n))
+    if (col_addressing_ok(g))
         launch_hb_mode<T, true>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, st);
     else
         launch_hb_mode<T, false>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, st);
@@ -637,7 +664,7 @@ template <class T>
 static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, hipStream_t st)
 {
     const Links<T> U = links_of<T>(a);
-    if (col_addressing_ok(a.n))
+    if (col_addressing_ok(g))
         launch_or_mode<T, true>(U, g, mu, par, a.flags, st);
     else
         launch_or_mode<T, false>(U, g, mu, par, a.flags, st);
@@ -645,7 +672,7 @@ static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, hipSt
 
 void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st)
 {
-    const Geom g = make_geom(a.n, a.tile);
+    const Geom g = make_geom(a.n, a.tile, a.tile_y);
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const uint32_t lid16 = 16u * (uint32_t)a.lattice_id;
     const dim3 grid(blocks_for(g.half)), block(kBlock);
@@ -658,7 +685,7 @@ void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st)
 void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, const uint32_t *d_sweep,
                      int mu, int par, hipStream_t st)
 {
-    const Geom g = make_geom(a.n, a.tile);
+    const Geom g = make_geom(a.n, a.tile, a.tile_y);
     if (a.prec == kF32)
         launch_hb<float>(a, g, mu, par, beta, seed, sweep, d_sweep, st);
     else
@@ -667,7 +694,7 @@ void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t s
 
 void launch_overrelax(const LaunchArgs &a, int mu, int par, hipStream_t st)
 {
-    const Geom g = make_geom(a.n, a.tile);
+    const Geom g = make_geom(a.n, a.tile, a.tile_y);
     if (a.prec == kF32)
         launch_or<float>(a, g, mu, par, st);
     else
@@ -727,19 +754,27 @@ void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st)
 
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
 {
-    const Geom g = make_geom(a.n, a.tile);
+    const Geom g = make_geom(a.n, a.tile, a.tile_y);
     double *partials = reinterpret_cast<double *>(a.work + w.off_plaq);
-    if (a.prec == kF32)
-        plaquette_kernel<float><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
-    else
-        plaquette_kernel<double><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
+    const bool col = col_addressing_ok(g);
+    if (a.prec == kF32) {
+        if (col)
+            plaquette_kernel<float, true><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
+        else
+            plaquette_kernel<float, false><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
+    } else {
+        if (col)
+            plaquette_kernel<double, true><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
+        else
+            plaquette_kernel<double, false><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
+    }
     colsum_kernel<<<6, kBlock, 0, st>>>(partials, w.nblk_plaq, 6, 1.0 / (double)a.volume, d_out + 1);
     plaq_total_kernel<<<1, 64, 0, st>>>(d_out);
 }
 
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st)
 {
-    const Geom g = make_geom(a.n, a.tile);
+    const Geom g = make_geom(a.n, a.tile, a.tile_y);
     double *Lf = reinterpret_cast<double *>(a.work + w.off_lfield);
     double *pp = reinterpret_cast<double *>(a.work + w.off_poly);
     if (a.prec == kF32)

@@ -23,6 +23,7 @@ struct LaunchArgs {
     int prec;
     int lattice_id;
     int tile;
+    int tile_y;
     uint64_t volume;
     void *links;
     char *work;

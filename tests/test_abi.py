@@ -51,10 +51,10 @@ def test_sizes(su2):
     assert su2.su2_links_bytes((256, 256, 256, 254), "f32") > 0
 
 
-def _desc(su2, n=(8, 8, 8, 8), prec=0, lid=0, links=0x10000, work=0x20000, wb=None, tile=0):
+def _desc(su2, n=(8, 8, 8, 8), prec=0, lid=0, links=0x10000, work=0x20000, wb=None, tile=0, tile_y=0):
     if wb is None:
         wb = su2.su2_workspace_bytes(n, 0) if all(v >= 2 and v % 2 == 0 for v in n) else 1 << 20
-    return su2.su2_lattice_t((ctypes.c_int32 * 4)(*n), prec, lid, tile, 0, links, work, wb)
+    return su2.su2_lattice_t((ctypes.c_int32 * 4)(*n), prec, lid, tile, tile_y, links, work, wb)
 
 
 def test_argument_checks_reject_before_any_hip_call(su2):
@@ -101,6 +101,9 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     # tile: a positive strip width must divide Nz
     assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 12, 8), tile=5)), s) == su2.SU2_EINVAL
     assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 12, 8), tile=24)), s) == su2.SU2_EINVAL
+    # tile_y: 0 or a divisor of Ny
+    for ty in (-1, 3, 16):
+        assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 12, 8), tile_y=ty)), s) == su2.SU2_EINVAL
     # batches
     d0, d1 = _desc(su2), _desc(su2, n=(4, 4, 4, 6), lid=1)
     arr = (su2.su2_lattice_t * 2)(d0, d1)

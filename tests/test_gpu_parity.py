@@ -340,10 +340,12 @@ def test_full_size_64(su2, prec):
 def test_block_order_does_not_change_results(su2, prec):
     # links of one class are independent, so every walk order must give
     # bit-identical links; plaquette sums differ only in summation order
+    # (walks with row ranges of 256/S cb indices: S <= 4 column-addressed,
+    # S = 8, 16 coordinate-addressed)
     n = (32, 16, 8, 4)
     links, plaqs = [], []
-    for w in (-1, 0, 1, 2, 4, 8):
-        lat = su2.Lattice(n, prec, device="cuda", tile=w)
+    for w, sy in ((-1, 0), (0, 0), (1, 0), (2, 0), (4, 0), (8, 0), (1, 2), (8, 4), (2, 8), (4, 16)):
+        lat = su2.Lattice(n, prec, device="cuda", tile=w, tile_y=sy)
         su2.su2_init_hot(lat, 5)
         su2.su2_heatbath_sweep(lat, 2.3, 5, 0)
         su2.su2_overrelax(lat, 2)
@@ -474,11 +476,11 @@ def test_autotuner_picks_a_valid_walk(su2, tmp_path):
     from paper_1104_5432_amd import autotune
     n = (16, 16, 16, 8)
     cache = str(tmp_path / "tiles.json")
-    tile = autotune.tune(n, "f32", cache=cache, reps=2)
-    assert tile in autotune.candidates(n)
-    assert autotune.tune(n, "f32", cache=cache) == tile          # cached
+    walk = autotune.tune(n, "f32", cache=cache, reps=2)
+    assert walk in autotune.candidates(n)
+    assert autotune.tune(n, "f32", cache=cache) == walk          # cached
     # the tuned walk changes no result
-    a = su2.Lattice(n, "f32", device="cuda", tile=tile)
+    a = su2.Lattice(n, "f32", device="cuda", tile=walk[0], tile_y=walk[1])
     b = su2.Lattice(n, "f32", device="cuda", tile=-1)
     for lat in (a, b):
         su2.su2_init_hot(lat, 3)
