@@ -37,7 +37,10 @@ def parse():
     ap.add_argument("--or-per-hb", type=int, default=4)
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-shape", type=str, default="48,48,48,48")
+    ap.add_argument("--cpu-shape", type=str, default=None,
+                    help="lattice of the CPU-oracle sample (default: the benchmarked lattice)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum wall time of the CPU-oracle sample (whole steps)")
     ap.add_argument("--start", choices=["hot", "cold"], default="hot")
     ap.add_argument("--tile", type=int, default=0,
                     help="walk of the single lattice: 0 default strip, > 0 strip width, < 0 plain order")
@@ -56,14 +59,17 @@ def parse():
     return ap.parse_args()
 
 
+SWEEP_SOURCES = ("su2_device.hpp", "su2_kernels.hip", "su2_launch.hpp")
+
+
 def csrc_sha256():
-    """Hash of the kernel sources, to tell whether a stored counter profile is current."""
-    import glob
+    """Hash of the sources of the sweep and observable kernels, to tell
+    whether a stored counter profile is current."""
     import hashlib
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", "*"))):
-        h.update(os.path.basename(path).encode())
-        with open(path, "rb") as f:
+    for name in SWEEP_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
@@ -85,28 +91,33 @@ def profiled_traffic(kernel, prec, shape):
     return None
 
 
-def cpu_baseline(shape, beta, seed, n_or):
-    """The FP64 CPU oracle timed on a bounded sample of the same workload."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(shape, beta, seed, n_or, min_seconds=10.0):
+    """The FP64 CPU oracle timed on a bounded sample of the same workload:
+    whole steps (1 heat-bath + n_or overrelaxation sweeps + plaquette +
+    Polyakov loop/correlator) on the same lattice, repeated until at least
+    min_seconds of wall time have been spent."""
     import oracle
     n = tuple(int(v) for v in shape.split(","))
     vol = n[0] * n[1] * n[2] * n[3]
     U = oracle.init_hot(n, seed)
-    t0 = time.perf_counter()
-    oracle.heatbath_sweep(n, U, beta, seed, 0)
-    for _ in range(n_or):
-        oracle.overrelax_sweep(n, U)
-    oracle.plaquette(n, U)
-    oracle.polyakov_corr(n, U)
-    dt = time.perf_counter() - t0
-    updates = 4 * vol * (1 + n_or)
+    steps, dt = 0, 0.0
+    while dt < min_seconds:
+        t0 = time.perf_counter()
+        oracle.heatbath_sweep(n, U, beta, seed, steps)
+        for _ in range(n_or):
+            oracle.overrelax_sweep(n, U)
+        oracle.plaquette(n, U)
+        oracle.polyakov_corr(n, U)
+        dt += time.perf_counter() - t0
+        steps += 1
+    updates = 4 * vol * (1 + n_or) * steps
     return {
         "value": updates / dt,
         "unit": "link updates/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"{'x'.join(map(str, n))} FP64 oracle, hot start, one step "
-                  f"(1 HB + {n_or} OR sweeps + plaquette + Polyakov/correlator), {dt:.2f} s wall",
+        "sample": f"{'x'.join(map(str, n))} FP64 oracle, hot start, {steps} step(s) of 1 HB + {n_or} OR "
+                  f"sweeps + plaquette + Polyakov/correlator, {dt:.1f} s wall",
     }
 
 
@@ -400,7 +411,8 @@ def main():
         "check": {"plaquette_last": last_plaq, "polyakov_abs_last": last_poly, "flags": flags},
     }
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(args.cpu_shape, args.beta, args.seed, args.or_per_hb)
+        rec["cpu_baseline"] = cpu_baseline(args.cpu_shape or args.shape, args.beta, args.seed, args.or_per_hb,
+                                           args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 
 

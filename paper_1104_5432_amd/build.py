@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsu2.so")
-SOURCES = ["su2_kernels.hip", "su2_learned.hip", "su2_api.cpp"]
+SOURCES = ["su2_kernels.hip", "su2_observables.hip", "su2_learned.hip", "su2_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

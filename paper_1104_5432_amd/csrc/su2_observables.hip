@@ -1,0 +1,238 @@
+// su2_observables.hip -- gfx950 kernels of the measured observables: the
+// mean plaquette (per plane), the Polyakov loop and its on-axis correlator.
+// All sums are FP64 and deterministic: wave64 shuffles, an LDS tree, one
+// partial per block (stored column by column) and a fixed-order final pass.
+#include "su2_device.hpp"
+#include "su2_launch.hpp"
+
+namespace su2 {
+
+template <class T>
+static Links<T> links_of(const LaunchArgs &a)
+{
+    Links<T> L;
+    L.p = reinterpret_cast<decltype(L.p)>(a.links);
+    L.half = (uint32_t)(a.volume / 2);
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the block; thread 0 returns the totals.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[NV])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = wave_sum(v[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            lds[wave][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w)
+                s += lds[w][j];
+            v[j] = s;
+        }
+    }
+}
+
+// Plaquettes: every site x sums (1/2) Tr of its six plaquettes
+// U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+, mu < nu, in FP64.  A thread
+// takes one cb index and both parities; blocks walk the lattice in the
+// same order as the update kernels; one partial per block.
+template <class T, class A>
+__device__ __forceinline__ void plaquette_site(const Links<T> &U, const A &ad, int par, double (&acc)[6])
+{
+    const int opp = par ^ 1;
+    const uint32_t own = ad.at(0, 0, 0, 0);
+    Quat<T> u[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+        u[mu] = ad.ld(U, mu, par, own);
+    const uint32_t ip[4] = {ad.at(1, 0, 0, 0), ad.at(0, 1, 0, 0), ad.at(0, 0, 1, 0), ad.at(0, 0, 0, 1)};
+    int p = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+        for (int nu = mu + 1; nu < 4; ++nu) {
+            const Quat<T> a = qmul(u[mu], ad.ld(U, nu, opp, ip[mu]));
+            const Quat<T> b = qmul(u[nu], ad.ld(U, mu, opp, ip[nu]));
+            acc[p++] += (double)qdot(a, b);
+        }
+}
+
+template <class T, bool COL>
+__global__ __launch_bounds__(kBlock) void plaquette_kernel(Links<T> U, Geom g, double *partials)
+{
+    __shared__ double lds[kBlock / 64][6];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i < g.half) {
+        if constexpr (COL) {
+#pragma unroll
+            for (int par = 0; par < 2; ++par)
+                plaquette_site(U, col_addr(g, i, par), par, acc);
+        } else {
+            CbAddr ad;
+            ad.cb = walk_cb(i, g.ord);
+            ad.g = &g;
+#pragma unroll
+            for (int par = 0; par < 2; ++par) {
+                ad.s = site_of_cb(g, ad.cb, par);
+                plaquette_site(U, ad, par, acc);
+            }
+        }
+    }
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            partials[(size_t)j * gridDim.x + blockIdx.x] = acc[j];
+}
+
+// Polyakov loop at each spatial site: ordered product of the Nt temporal links.
+template <class T>
+__global__ __launch_bounds__(kBlock) void polyakov_kernel(Links<T> U, Geom g, double *Lfield, double *partials)
+{
+    __shared__ double lds[kBlock / 64][2];
+    double acc[2] = {0, 0};
+    for (uint32_t sp = blockIdx.x * kBlock + threadIdx.x; sp < g.vs; sp += gridDim.x * kBlock) {
+        const uint32_t yz = fdiv(sp, g.div_nx);
+        const uint32_t x = sp - yz * (uint32_t)g.n[0];
+        const uint32_t z = fdiv(yz, g.div_ny);
+        const uint32_t y = yz - z * (uint32_t)g.n[1];
+        Quat<T> P = {1, 0, 0, 0};
+        for (int t = 0; t < g.n[3]; ++t) {
+            const uint32_t site = sp + g.vs * (uint32_t)t;
+            const int par = (int)((x + y + z + (uint32_t)t) & 1u);
+            P = qmul(P, U.ld(3, par, site >> 1));
+        }
+        const double L = (double)P.w;
+        Lfield[sp] = L;
+        acc[0] += L;
+        acc[1] += fabs(L);
+    }
+    block_sum<2>(acc, lds);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = acc[0];
+        partials[(size_t)gridDim.x + blockIdx.x] = acc[1];
+    }
+}
+
+// On-axis Polyakov correlator: for r = 1..R, sum_x L(x)(L(x+r e_x) + L(x+r e_y) + L(x+r e_z)).
+__global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, Geom g, int R, double *partials)
+{
+    __shared__ double lds[kBlock / 64][1];
+    const uint32_t nx = (uint32_t)g.n[0], ny = (uint32_t)g.n[1], nz = (uint32_t)g.n[2];
+    for (int r = 1; r <= R; ++r) {
+        double acc[1] = {0.0};
+        for (uint32_t sp = blockIdx.x * kBlock + threadIdx.x; sp < g.vs; sp += gridDim.x * kBlock) {
+            const uint32_t yz = fdiv(sp, g.div_nx);
+            const uint32_t x = sp - yz * nx;
+            const uint32_t z = fdiv(yz, g.div_ny);
+            const uint32_t y = yz - z * ny;
+            const uint32_t xr = x + (uint32_t)r, yr = y + (uint32_t)r, zr = z + (uint32_t)r;
+            const uint32_t xs = xr >= nx ? xr - nx : xr;
+            const uint32_t ys = yr >= ny ? yr - ny : yr;
+            const uint32_t zs = zr >= nz ? zr - nz : zr;
+            const double L = Lfield[sp];
+            acc[0] += L * (Lfield[xs + nx * (y + ny * z)] + Lfield[x + nx * (ys + ny * z)] +
+                           Lfield[x + nx * (y + ny * zs)]);
+        }
+        block_sum<1>(acc, lds);
+        if (threadIdx.x == 0)
+            partials[(size_t)(r - 1) * gridDim.x + blockIdx.x] = acc[0];
+        __syncthreads();
+    }
+}
+
+// out[c] = scale * sum_b partials[c*nblk + b] (partials stored column by
+// column, so the reads are contiguous), one block per column, fixed order.
+__global__ __launch_bounds__(kBlock) void colsum_kernel(const double *partials, uint32_t nblk, double scale,
+                                                         double *out)
+{
+    __shared__ double lds[kBlock / 64][1];
+    const double *col = partials + (size_t)blockIdx.x * nblk;
+    double acc[1] = {0.0};
+    // Eight loads are issued before their (in-order) sums; one load per
+    // iteration made the loop a chain of dependent global-memory latencies.
+    uint32_t b = threadIdx.x;
+    for (; b + 7u * kBlock < nblk; b += 8u * kBlock) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = col[b + (uint32_t)u * kBlock];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            acc[0] += v[u];
+    }
+    for (; b < nblk; b += kBlock)
+        acc[0] += col[b];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = acc[0] * scale;
+}
+
+// d_out[0] = mean of the six plane averages d_out[1..6].
+__global__ void plaq_total_kernel(double *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        out[0] = (out[1] + out[2] + out[3] + out[4] + out[5] + out[6]) / 6.0;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
+{
+    const Geom g = make_geom(a.n, a.tile, a.tile_y);
+    double *partials = reinterpret_cast<double *>(a.work + w.off_plaq);
+    const bool col = col_addressing_ok(g);
+    if (a.prec == kF32) {
+        if (col)
+            plaquette_kernel<float, true><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
+        else
+            plaquette_kernel<float, false><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
+    } else {
+        if (col)
+            plaquette_kernel<double, true><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
+        else
+            plaquette_kernel<double, false><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
+    }
+    colsum_kernel<<<6, kBlock, 0, st>>>(partials, w.nblk_plaq, 1.0 / (double)a.volume, d_out + 1);
+    plaq_total_kernel<<<1, 64, 0, st>>>(d_out);
+}
+
+void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st)
+{
+    const Geom g = make_geom(a.n, a.tile, a.tile_y);
+    double *Lf = reinterpret_cast<double *>(a.work + w.off_lfield);
+    double *pp = reinterpret_cast<double *>(a.work + w.off_poly);
+    if (a.prec == kF32)
+        polyakov_kernel<float><<<w.nblk_poly, kBlock, 0, st>>>(links_of<float>(a), g, Lf, pp);
+    else
+        polyakov_kernel<double><<<w.nblk_poly, kBlock, 0, st>>>(links_of<double>(a), g, Lf, pp);
+    colsum_kernel<<<2, kBlock, 0, st>>>(pp, w.nblk_poly, 1.0 / (double)g.vs, d_out);
+    if (d_corr && w.rmax > 0) {
+        double *cp = reinterpret_cast<double *>(a.work + w.off_corr);
+        polycorr_kernel<<<w.nblk_corr, kBlock, 0, st>>>(Lf, g, w.rmax, cp);
+        colsum_kernel<<<w.rmax, kBlock, 0, st>>>(cp, w.nblk_corr, 1.0 / (3.0 * (double)g.vs), d_corr);
+    }
+}
+
+} // namespace su2
