@@ -1,0 +1,95 @@
+"""Finite-temperature analysis (section "Finite Temperature", eqs. (2)-(3) and
+the fits after them), pinned without the paper's data (its figures are not
+available): closed forms, exact recovery of known parameters, identities of
+the jackknife, and the property the renormalisation exists for.
+
+The absolute sigma(T) values of the paper stay unpinned: they need its
+configurations.  What is pinned is the procedure."""
+import numpy as np
+import pytest
+
+from paper_1104_5432_amd import analysis as an
+
+
+def test_renormalisation_removes_the_nt_dependence():
+    # eq. (2): if the bare loop carries a self-energy factor Z(g^2)^-Nt on top
+    # of a function of T alone, the renormalised loop is the same for every
+    # Nt; with the paper's A, B at g^2 = 4/beta.
+    f_T = 0.4
+    for beta in (2.4, 2.6, 3.2, 4.0):
+        z = an.renormalization_z(beta)
+        g2 = 4.0 / beta
+        assert z == pytest.approx(np.exp(0.0637 * g2 + 0.0731 * g2 ** 2), rel=1e-15)
+        lr = [an.renormalized_polyakov(f_T * z ** -nt, beta, nt) for nt in (4, 6, 8, 12)]
+        assert np.allclose(lr, f_T, rtol=1e-13)
+    # weak coupling: Z -> 1
+    assert an.renormalization_z(1e9) == pytest.approx(1.0, abs=1e-8)
+
+
+def test_free_energy_inverts_the_correlator():
+    nt, a0, a1, sig = 6, 0.31, 0.27, 0.055
+    r = np.arange(1.0, 13.0)
+    aF = a0 - a1 / r + sig * r
+    # C(r) = (1/4)<TrL TrL^+> with the ln 4 shift: F/T = -ln C - ln 4
+    C = np.exp(-(aF * nt) - np.log(4.0))
+    assert np.allclose(an.free_energy_lattice(C, nt), aF, rtol=0, atol=1e-14)
+    # a rescaling of C only shifts a0 (the undetermined constant)
+    p, _, _ = an.fit_string_tension(r, an.free_energy_lattice(3.0 * C, nt))
+    assert p[0] == pytest.approx(a0 - np.log(3.0) / nt, abs=1e-12)
+    assert p[1] == pytest.approx(a1, abs=1e-12)
+    assert p[2] == pytest.approx(sig, abs=1e-12)
+
+
+def test_string_tension_fit_is_exact_on_exact_data_and_unbiased_with_noise():
+    r = np.arange(1.0, 17.0)
+    truth = np.array([0.4, 0.3, 0.06])
+    F = truth[0] - truth[1] / r + truth[2] * r
+    p, cov, chi2 = an.fit_string_tension(r, F)
+    assert np.allclose(p, truth, atol=1e-12) and chi2 < 1e-20
+    rng = np.random.default_rng(11)
+    dF = 0.01 * (1 + 0.1 * r)
+    pulls, chis = [], []
+    for _ in range(400):
+        p, cov, chi2 = an.fit_string_tension(r, F + rng.normal(size=r.size) * dF, dF)
+        pulls.append((p - truth) / np.sqrt(np.diag(cov)))
+        chis.append(chi2)
+    pulls = np.array(pulls)
+    # pulls ~ N(0,1): mean within 4/sqrt(400), variance within 25%
+    assert np.all(np.abs(pulls.mean(0)) < 0.2)
+    assert np.all(np.abs(pulls.var(0) - 1.0) < 0.25)
+    assert abs(np.mean(chis) - 1.0) < 0.1
+
+
+def test_jackknife_of_a_mean_is_the_standard_error_of_block_means():
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=(1000, 3))
+    est, err = an.jackknife(lambda m: m, x, n_blocks=20)
+    blocks = x.reshape(20, 50, 3).mean(1)
+    assert np.allclose(est, x.mean(0), atol=1e-15)
+    assert np.allclose(err, blocks.std(0, ddof=1) / np.sqrt(20), rtol=1e-12)
+
+
+def test_string_tension_from_per_sweep_correlators():
+    # synthetic per-sweep correlators around a known potential: the
+    # jackknife fit recovers sigma within its error
+    rng = np.random.default_rng(5)
+    nt, r = 4, np.arange(1.0, 9.0)
+    aF = 0.5 - 0.2 / r + 0.08 * r
+    C = np.exp(-aF * nt - np.log(4.0))
+    samples = C * (1 + 0.01 * rng.normal(size=(2000, r.size)))
+    p, perr, (rr, F, dF) = an.string_tension(samples, nt)
+    assert np.all(dF > 0) and np.allclose(rr, r)
+    assert abs(p[2] - 0.08) < 4 * perr[2]
+    assert perr[2] < 0.01
+
+
+@pytest.mark.parametrize("ansatz,truth", [("sqrt", (0.6976, 0.9990)), ("critical", (1.5541, -0.5122))])
+def test_sigma_of_t_ansatz_fits_recover_the_papers_parameters(ansatz, truth):
+    # data generated from the paper's fitted parameters are fitted back
+    t = np.linspace(0.3, 0.95, 12)
+    f = an.sigma_ansatz_sqrt if ansatz == "sqrt" else an.sigma_ansatz_critical
+    s = f(t, *truth)
+    p, perr, chi2 = an.fit_sigma_of_t(t, s, np.full_like(t, 1e-4), ansatz=ansatz)
+    assert np.allclose(p, truth, rtol=1e-6, atol=1e-6) and chi2 < 1e-6
+    # sqrt ansatz: sigma(Tc) = a sqrt(1 - b) ~ 0 for b ~ 1; critical: sigma(Tc) = 0
+    assert f(np.array([1.0]), *truth)[0] < 0.03
