@@ -660,12 +660,20 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, cons
     return staple<T, MU>(U, ad, par);
 }
 
-// Residency cap of the overrelaxation kernels.  At the 7 blocks per CU their
-// registers allow, the blocks in flight on an XCD touch more links than its
-// 4 MB L2 holds and neighbours are evicted between uses; 4 blocks per CU
-// (16 waves) is faster (FP32 3%, FP64 5%, measured at 64^4 and 96^4).  The
-// cap is an LDS reservation: 36 KB per block, 4 blocks in 160 KB.
+// Residency cap of the overrelaxation kernel on large lattices.  At the 7
+// blocks per CU its registers allow, the blocks in flight on an XCD touch
+// more links than its 4 MB L2 holds and neighbours are evicted between uses;
+// 4 blocks per CU (16 waves) is faster for one large lattice (64^4: FP32 3%,
+// FP64 5%; 96^4: 3%).  For small lattices, and the batched kernel over many
+// of them, the cap costs more latency hiding than it saves (a batch of
+// 0.1-2 M-site lattices: 10% slower), so it applies from 2^21 links per
+// class.  The cap is an LDS reservation: 36 KB per block, 4 blocks in 160 KB.
 constexpr int kOrResidencyLds = 36 * 1024;
+
+__host__ inline bool residency_cap_pays(const Geom &g)
+{
+    return g.half >= (1u << 21);
+}
 
 __device__ __forceinline__ void reserve_lds_for_residency()
 {

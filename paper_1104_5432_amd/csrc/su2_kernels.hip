@@ -301,19 +301,29 @@ __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, in
     heatbath_body<T, MU, COL>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x);
 }
 
-template <class T, int MU, bool COL>
+template <class T, int MU, bool COL, bool CAP>
 __global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags)
 {
-    reserve_lds_for_residency();
+    if constexpr (CAP)
+        reserve_lds_for_residency();
     overrelax_body<T, MU, COL>(U, g, par, flags, blockIdx.x, gridDim.x);
 }
 
+// The block's lattice: entries are ordered by block0 (strictly increasing,
+// entry 0 at block 0), so it is the last entry with block0 <= blockIdx.x.
+// Each lane tests one entry and a wave ballot counts the hits: one round of
+// independent loads for up to 64 lattices instead of a chain of dependent
+// ones (which, exposed at low residency, cost more than the update).
 __device__ __forceinline__ const BatchEntry &find_entry(const BatchEntry *tab, int count)
 {
-    int j = 0;
-    while (j + 1 < count && blockIdx.x >= tab[j + 1].block0)
-        ++j;
-    return tab[j];
+    const int lane = (int)(threadIdx.x & 63u);
+    int hits = 0;
+    for (int base = 0; base < count; base += 64) {
+        const int j = base + lane;
+        const bool le = j < count && tab[j].block0 <= blockIdx.x;
+        hits += (int)__popcll(__ballot(le));
+    }
+    return tab[__builtin_amdgcn_readfirstlane(hits > 0 ? hits - 1 : 0)];
 }
 
 template <class T, int MU>
@@ -337,7 +347,6 @@ __global__ __launch_bounds__(kBlock) void heatbath_batch_kernel(const BatchEntry
 template <class T, int MU>
 __global__ __launch_bounds__(kBlock) void overrelax_batch_kernel(const BatchEntry *tab, int count, int par)
 {
-    reserve_lds_for_residency();
     const BatchEntry &e = find_entry(tab, count);
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(e.links);
@@ -466,15 +475,15 @@ static void launch_hb(const LaunchArgs &a, const Geom &g, int mu, int par, doubl
         launch_hb_mode<T, false>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, st);
 }
 
-template <class T, bool COL>
+template <class T, bool COL, bool CAP>
 static void launch_or_mode(const Links<T> &U, const Geom &g, int mu, int par, uint32_t *flags, hipStream_t st)
 {
     const dim3 grid(blocks_for(g.half)), block(kBlock);
     switch (mu) {
-    case 0: overrelax_kernel<T, 0, COL><<<grid, block, 0, st>>>(U, g, par, flags); break;
-    case 1: overrelax_kernel<T, 1, COL><<<grid, block, 0, st>>>(U, g, par, flags); break;
-    case 2: overrelax_kernel<T, 2, COL><<<grid, block, 0, st>>>(U, g, par, flags); break;
-    default: overrelax_kernel<T, 3, COL><<<grid, block, 0, st>>>(U, g, par, flags); break;
+    case 0: overrelax_kernel<T, 0, COL, CAP><<<grid, block, 0, st>>>(U, g, par, flags); break;
+    case 1: overrelax_kernel<T, 1, COL, CAP><<<grid, block, 0, st>>>(U, g, par, flags); break;
+    case 2: overrelax_kernel<T, 2, COL, CAP><<<grid, block, 0, st>>>(U, g, par, flags); break;
+    default: overrelax_kernel<T, 3, COL, CAP><<<grid, block, 0, st>>>(U, g, par, flags); break;
     }
 }
 
@@ -482,10 +491,18 @@ template <class T>
 static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, hipStream_t st)
 {
     const Links<T> U = links_of<T>(a);
-    if (col_addressing_ok(g))
-        launch_or_mode<T, true>(U, g, mu, par, a.flags, st);
-    else
-        launch_or_mode<T, false>(U, g, mu, par, a.flags, st);
+    const bool cap = residency_cap_pays(g);
+    if (col_addressing_ok(g)) {
+        if (cap)
+            launch_or_mode<T, true, true>(U, g, mu, par, a.flags, st);
+        else
+            launch_or_mode<T, true, false>(U, g, mu, par, a.flags, st);
+    } else {
+        if (cap)
+            launch_or_mode<T, false, true>(U, g, mu, par, a.flags, st);
+        else
+            launch_or_mode<T, false, false>(U, g, mu, par, a.flags, st);
+    }
 }
 
 void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st)
