@@ -46,8 +46,9 @@ def parse():
                     help="walk of the single lattice: 0 default strip, > 0 strip width, < 0 plain order")
     ap.add_argument("--tile-y", type=int, default=0,
                     help="row ranges per column in strip order (divides Ny; 0 default)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="choose the walk with paper_1104_5432_amd.autotune before timing (untimed)")
+    ap.add_argument("--autotune", action=argparse.BooleanOptionalAction, default=True,
+                    help="choose the walk with paper_1104_5432_amd.autotune before timing (untimed; "
+                         "--no-autotune uses --tile/--tile-y)")
     ap.add_argument("--train", type=int, default=10000,
                     help="learned workload: heat-bath configurations to train on")
     ap.add_argument("--workload", choices=["single", "scan", "learned"], default="single",
@@ -74,12 +75,13 @@ def csrc_sha256():
     return h.hexdigest()
 
 
-def profiled_traffic(kernel, prec, shape):
+def profiled_traffic(kernel, prec, shape, walk):
     """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE/WRITE_SIZE
     summaries under profiles/ (copy-calibrated), or None when no summary was
-    taken from the current kernel sources."""
+    taken from the current kernel sources with this lattice and walk."""
     import glob
-    want = {"kernel": kernel, "prec": prec, "shape": shape, "csrc_sha256": csrc_sha256()}
+    want = {"kernel": kernel, "prec": prec, "shape": shape, "walk": "%d,%d" % tuple(walk),
+            "csrc_sha256": csrc_sha256()}
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as f:
             for line in f:
@@ -293,7 +295,7 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     tile, tile_y = args.tile, args.tile_y
-    if args.autotune:
+    if args.autotune and not (args.tile or args.tile_y):
         from paper_1104_5432_amd import autotune
         tile, tile_y = autotune.tune(n, args.prec, device=dev)
     lat = su2.Lattice(n, args.prec, device=dev, tile=tile, tile_y=tile_y)
@@ -364,7 +366,7 @@ def main():
         "kernel": "overrelax_kernel",
         "achieved": or_gbs,
         "frac": or_gbs / HBM_PEAK_GBS,
-        "traffic": profiled_traffic("overrelax_kernel", args.prec, args.shape),
+        "traffic": profiled_traffic("overrelax_kernel", args.prec, args.shape, (tile, tile_y)),
         "bytes_per_launch": or_bytes,
         "avg_launch_ms": or_launch_ms,
     }
@@ -372,7 +374,7 @@ def main():
         "kernel": "heatbath_kernel",
         "achieved": hb_gbs,
         "frac": hb_gbs / HBM_PEAK_GBS,
-        "traffic": profiled_traffic("heatbath_kernel", args.prec, args.shape),
+        "traffic": profiled_traffic("heatbath_kernel", args.prec, args.shape, (tile, tile_y)),
         "bytes_per_launch": hb_bytes,
         "avg_launch_ms": hb_launch_ms,
     }

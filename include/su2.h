@@ -83,9 +83,10 @@ typedef struct su2_lattice {
                             on it): 0 = default, W > 0 = (z,t) columns in
                             z-strips of width W (W must divide Nz), < 0 =
                             plain checkerboard-index order */
-    int32_t tile_y;      /* in strip order (tile >= 0): each column is walked
-                            as tile_y ranges of Ny/tile_y rows (tile_y must
-                            divide Ny; 0 = default); performance only */
+    int32_t tile_y;      /* in strip order (tile >= 0): the update kernels
+                            walk each column as tile_y ranges of Ny/tile_y
+                            rows (tile_y must divide Ny; 0 = default);
+                            performance only */
     void *links;         /* device, >= su2_links_bytes(n, prec) */
     void *work;          /* device, >= su2_workspace_bytes(n, prec) */
     uint64_t work_bytes; /* size of work in bytes */

@@ -9,7 +9,7 @@ sweep on a scratch lattice (hot start, never the caller's lattice) after a
 warm-up, timed with HIP events on the current stream; the fastest total
 wins.  The walk changes no result, only the order in which blocks visit the
 lattice, so tuning is safe to apply to any chain.  Choices are cached in a
-JSON file keyed by device name, extents and precision.
+JSON file keyed by device architecture, CU count, extents and precision.
 """
 import json
 import os
@@ -18,7 +18,9 @@ import torch
 
 from . import (Lattice, su2_heatbath_sweep, su2_init_hot, su2_overrelax)
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "su2_mi355x", "tiles.json")
+# The cache file: $SU2_AUTOTUNE_CACHE, else ~/.cache/su2_mi355x/tiles.json.
+DEFAULT_CACHE = os.environ.get("SU2_AUTOTUNE_CACHE") or os.path.join(
+    os.path.expanduser("~"), ".cache", "su2_mi355x", "tiles.json")
 
 
 def candidates(n):
@@ -35,8 +37,11 @@ def candidates(n):
 
 
 def _key(n, prec, device):
-    name = torch.cuda.get_device_name(torch.device(device))
-    return f"{name}|{'x'.join(str(int(v)) for v in n)}|{prec}"
+    # architecture and CU count: the marketing name can differ between
+    # processes on the same device (e.g. under a profiler)
+    p = torch.cuda.get_device_properties(torch.device(device))
+    arch = getattr(p, "gcnArchName", "") or p.name
+    return f"{arch}|{p.multi_processor_count}cu|{'x'.join(str(int(v)) for v in n)}|{prec}"
 
 
 def _load(path):
