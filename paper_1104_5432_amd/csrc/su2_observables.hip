@@ -134,31 +134,31 @@ __global__ __launch_bounds__(kBlock) void polyakov_kernel(Links<T> U, Geom g, do
     }
 }
 
-// On-axis Polyakov correlator: for r = 1..R, sum_x L(x)(L(x+r e_x) + L(x+r e_y) + L(x+r e_z)).
-__global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, Geom g, int R, double *partials)
+// On-axis Polyakov correlator: for r = 1..R (blockIdx.y = r - 1),
+// sum_x L(x)(L(x+r e_x) + L(x+r e_y) + L(x+r e_z)); one partial per block,
+// stored column r-1.
+__global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, Geom g, double *partials)
 {
     __shared__ double lds[kBlock / 64][1];
     const uint32_t nx = (uint32_t)g.n[0], ny = (uint32_t)g.n[1], nz = (uint32_t)g.n[2];
-    for (int r = 1; r <= R; ++r) {
-        double acc[1] = {0.0};
-        for (uint32_t sp = blockIdx.x * kBlock + threadIdx.x; sp < g.vs; sp += gridDim.x * kBlock) {
-            const uint32_t yz = fdiv(sp, g.div_nx);
-            const uint32_t x = sp - yz * nx;
-            const uint32_t z = fdiv(yz, g.div_ny);
-            const uint32_t y = yz - z * ny;
-            const uint32_t xr = x + (uint32_t)r, yr = y + (uint32_t)r, zr = z + (uint32_t)r;
-            const uint32_t xs = xr >= nx ? xr - nx : xr;
-            const uint32_t ys = yr >= ny ? yr - ny : yr;
-            const uint32_t zs = zr >= nz ? zr - nz : zr;
-            const double L = Lfield[sp];
-            acc[0] += L * (Lfield[xs + nx * (y + ny * z)] + Lfield[x + nx * (ys + ny * z)] +
-                           Lfield[x + nx * (y + ny * zs)]);
-        }
-        block_sum<1>(acc, lds);
-        if (threadIdx.x == 0)
-            partials[(size_t)(r - 1) * gridDim.x + blockIdx.x] = acc[0];
-        __syncthreads();
+    const uint32_t r = blockIdx.y + 1u;
+    double acc[1] = {0.0};
+    for (uint32_t sp = blockIdx.x * kBlock + threadIdx.x; sp < g.vs; sp += gridDim.x * kBlock) {
+        const uint32_t yz = fdiv(sp, g.div_nx);
+        const uint32_t x = sp - yz * nx;
+        const uint32_t z = fdiv(yz, g.div_ny);
+        const uint32_t y = yz - z * ny;
+        const uint32_t xr = x + r, yr = y + r, zr = z + r;
+        const uint32_t xs = xr >= nx ? xr - nx : xr;
+        const uint32_t ys = yr >= ny ? yr - ny : yr;
+        const uint32_t zs = zr >= nz ? zr - nz : zr;
+        const double L = Lfield[sp];
+        acc[0] += L * (Lfield[xs + nx * (y + ny * z)] + Lfield[x + nx * (ys + ny * z)] +
+                       Lfield[x + nx * (y + ny * zs)]);
     }
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0)
+        partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
 }
 
 // out[c] = scale * sum_b partials[c*nblk + b] (partials stored column by
@@ -232,7 +232,7 @@ void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, do
     colsum_kernel<<<2, kBlock, 0, st>>>(pp, w.nblk_poly, 1.0 / (double)g.vs, d_out);
     if (d_corr && w.rmax > 0) {
         double *cp = reinterpret_cast<double *>(a.work + w.off_corr);
-        polycorr_kernel<<<w.nblk_corr, kBlock, 0, st>>>(Lf, g, w.rmax, cp);
+        polycorr_kernel<<<dim3(w.nblk_corr, (uint32_t)w.rmax), kBlock, 0, st>>>(Lf, g, cp);
         colsum_kernel<<<w.rmax, kBlock, 0, st>>>(cp, w.nblk_corr, 1.0 / (3.0 * (double)g.vs), d_corr);
     }
 }
