@@ -51,9 +51,10 @@ def parse():
                          "--no-autotune uses --tile/--tile-y)")
     ap.add_argument("--train", type=int, default=10000,
                     help="learned workload: heat-bath configurations to train on")
-    ap.add_argument("--workload", choices=["single", "scan", "learned"], default="single",
+    ap.add_argument("--workload", choices=["single", "scan", "learned", "precision"], default="single",
                     help="single: one lattice (--shape); scan: 16 lattices mixing 32^3x4, 48^3x6, "
-                         "64^3x8 at beta 2.2..2.7, one captured graph replay per sweep")
+                         "64^3x8 at beta 2.2..2.7, one captured graph replay per sweep; learned: the "
+                         "learned block proposal at 16^3x4; precision: FP32 against FP64 observables")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="bytes of a plain device copy to run before the timed region "
                          "(reference for hardware byte counters)")
@@ -273,6 +274,71 @@ def learned_workload(args):
     print(json.dumps(rec), flush=True)
 
 
+def precision_workload(args):
+    """FP32 against FP64 links on the benchmarked lattice: for beta 2.3, 2.5
+    and 6.0 an FP64 and an FP32 chain (hot start, args.steps steps of 1 heat
+    bath + args.or_per_hb overrelaxation sweeps) and the difference of their
+    mean plaquette and mean |L| in units of the combined Gamma-method error,
+    after discarding the first 20% of sweeps."""
+    import torch
+    import paper_1104_5432_amd as su2
+    from paper_1104_5432_amd.stats import gamma_method
+
+    n = tuple(int(v) for v in args.shape.split(","))
+    dev = torch.device("cuda:0")
+    rows = {}
+    t0 = time.perf_counter()
+    for beta in (2.3, 2.5, 6.0):
+        res = {}
+        for prec in ("f64", "f32"):
+            lat = su2.Lattice(n, prec, device=dev)
+            su2.su2_init_hot(lat, args.seed)
+            plaq = torch.empty((args.steps, 7), dtype=torch.float64, device=dev)
+            poly = torch.empty((args.steps, 2), dtype=torch.float64, device=dev)
+            for s in range(args.steps):
+                su2.su2_heatbath_sweep(lat, beta, args.seed, s)
+                su2.su2_overrelax(lat, args.or_per_hb)
+                su2.su2_plaquette(lat, plaq[s])
+                su2.su2_polyakov(lat, poly[s], with_corr=False)
+            torch.cuda.synchronize()
+            cut = args.steps // 5
+            res[prec] = {"plaquette": gamma_method(plaq[cut:, 0].cpu().numpy())[:2],
+                         "abs_polyakov": gamma_method(np.abs(poly[cut:, 0].cpu().numpy()))[:2],
+                         "flags": int(su2.su2_get_flags(lat).item())}
+            del lat
+        row = {}
+        for obs in ("plaquette", "abs_polyakov"):
+            (m64, e64), (m32, e32) = res["f64"][obs], res["f32"][obs]
+            row[obs] = {"f64": m64, "f64_err": e64, "f32": m32, "f32_err": e32, "diff": m32 - m64,
+                        "z": (m32 - m64) / float(np.hypot(e64, e32))}
+        row["flags"] = res["f64"]["flags"] | res["f32"]["flags"]
+        rows[str(beta)] = row
+        print(f"beta {beta}: {row}", file=sys.stderr, flush=True)
+    zmax = max(abs(r[o]["z"]) for r in rows.values() for o in ("plaquette", "abs_polyakov"))
+    rec = {
+        "metric": "FP32 - FP64 observable difference (max |z| over beta and observables)",
+        "value": zmax,
+        "unit": "combined standard errors",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.steps // 5,
+        "ms_per_step": 1e3 * (time.perf_counter() - t0) / (6 * args.steps),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 vs f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"SU(2) {'x'.join(map(str, n))}, hot start (Philox seed {args.seed}), FP32 and FP64 "
+                        f"chains of {args.steps} steps of 1 heat-bath + {args.or_per_hb} overrelaxation sweeps "
+                        "at beta 2.3, 2.5, 6.0; mean plaquette and mean |L|, Gamma-method errors",
+            "lattice": list(n),
+        },
+        "by_beta": rows,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -284,6 +350,9 @@ def main():
         return
     if args.workload == "learned":
         learned_workload(args)
+        return
+    if args.workload == "precision":
+        precision_workload(args)
         return
 
     import torch
