@@ -1,0 +1,41 @@
+"""bench.py's command line on a machine without a GPU: the one-GPU rule and
+the argument surface (no kernel runs here)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True,
+                          text=True, timeout=120)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_help_lists_the_workloads():
+    r = _run("--help")
+    assert r.returncode == 0
+    for w in ("single", "scan", "learned", "precision", "--autotune", "--tile-y"):
+        assert w in r.stdout
+
+
+def test_stored_traffic_lookup_matches_walk_and_sources(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    line = ("traffic: kernel=overrelax_kernel prec=f32 shape=8,8,8,8 walk=2,1 bytes_per_launch=1234 "
+            f"csrc_sha256={bench.csrc_sha256()}\n")
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "x.md").write_text("# t\n" + line)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "csrc_sha256", lambda: line.split("csrc_sha256=")[1].strip())
+    assert bench.profiled_traffic("overrelax_kernel", "f32", "8,8,8,8", (2, 1)) == 1234.0
+    assert bench.profiled_traffic("overrelax_kernel", "f32", "8,8,8,8", (2, 2)) is None
+    assert bench.profiled_traffic("heatbath_kernel", "f32", "8,8,8,8", (2, 1)) is None
+    monkeypatch.setattr(bench, "csrc_sha256", lambda: "0" * 64)
+    assert bench.profiled_traffic("overrelax_kernel", "f32", "8,8,8,8", (2, 1)) is None
