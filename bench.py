@@ -69,10 +69,13 @@ def csrc_sha256():
     whether a stored counter profile is current."""
     import hashlib
     h = hashlib.sha256()
-    for name in SWEEP_SOURCES:
-        h.update(name.encode())
-        with open(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    try:
+        for name in SWEEP_SOURCES:
+            h.update(name.encode())
+            with open(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", name), "rb") as f:
+                h.update(f.read())
+    except OSError:
+        return None
     return h.hexdigest()
 
 
@@ -81,8 +84,10 @@ def profiled_traffic(kernel, prec, shape, walk):
     summaries under profiles/ (copy-calibrated), or None when no summary was
     taken from the current kernel sources with this lattice and walk."""
     import glob
-    want = {"kernel": kernel, "prec": prec, "shape": shape, "walk": "%d,%d" % tuple(walk),
-            "csrc_sha256": csrc_sha256()}
+    digest = csrc_sha256()
+    if digest is None:
+        return None
+    want = {"kernel": kernel, "prec": prec, "shape": shape, "walk": "%d,%d" % tuple(walk), "csrc_sha256": digest}
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as f:
             for line in f:
