@@ -2,7 +2,8 @@
 
 One step = one pass of the whole path on a resident lattice: 1 heat-bath
 sweep (8 checkerboard launches) + 4 overrelaxation sweeps (32 launches) +
-mean plaquette + Polyakov loop and its on-axis correlator.  Default workload:
+mean plaquette, Polyakov loop and its on-axis correlator (one measurement
+pass over the links, su2_measure).  Default workload:
 64^4 periodic lattice, beta = 2.3, FP32 links, hot start (Philox seed 1234).
 The value counts 20 V link updates per step (4 V heat bath + 16 V
 overrelaxation); the per-kernel roofline uses the algorithmic bytes of each
@@ -398,8 +399,7 @@ def main():
         if ev:
             ev[2].record(stream)
         k = s - args.warmup if s >= args.warmup else 0
-        su2.su2_plaquette(lat, plaq[k])
-        su2.su2_polyakov(lat, poly[k], corr[k])
+        su2.su2_measure(lat, plaq[k], poly[k], corr[k])     # plaquette, Polyakov loop, correlator
 
     for s in range(args.warmup):
         step(s)

@@ -145,6 +145,15 @@ int su2_plaquette(const su2_lattice_t *lat, double *d_out, void *stream);
  * r = 1..R.  FP64 sums, fixed reduction order. */
 int su2_polyakov(const su2_lattice_t *lat, double *d_out, double *d_corr, void *stream);
 
+/* Both measurements of a configuration in one pass over the links (Sec. 2.1
+ * mean plaquette; Sec. 2.2 eqs. (1), (3)): d_plaq (device, 7 doubles) as
+ * su2_plaquette's d_out, d_poly (device, 2 doubles) as su2_polyakov's d_out,
+ * d_corr (optional) as su2_polyakov's.  Same quantities, FP64 sums in a
+ * different fixed order (so the values agree with the separate calls to a
+ * few ulp, not bitwise); each link is read once as its own site's link and
+ * the temporal links once for both the plaquettes and the Polyakov lines. */
+int su2_measure(const su2_lattice_t *lat, double *d_plaq, double *d_poly, double *d_corr, void *stream);
+
 /* ---- Batches: many independent lattices per launch (a temperature scan) ----
  * A batch is count lattice descriptors of one precision, each with its own
  * extents, beta, lattice_id (distinct ids give independent random streams;

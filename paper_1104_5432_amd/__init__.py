@@ -61,6 +61,7 @@ _SIGNATURES = {
     "su2_overrelax_halfsweep": (ctypes.c_int, [_LP, ctypes.c_int32, ctypes.c_int32, _VP]),
     "su2_plaquette": (ctypes.c_int, [_LP, _VP, _VP]),
     "su2_polyakov": (ctypes.c_int, [_LP, _VP, _VP, _VP]),
+    "su2_measure": (ctypes.c_int, [_LP, _VP, _VP, _VP, _VP]),
     "su2_get_flags": (ctypes.c_int, [_LP, _VP, _VP]),
     "su2_batch_table_bytes": (ctypes.c_uint64, [ctypes.c_int32]),
     "su2_batch_fill": (ctypes.c_int, [_LP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _VP, ctypes.c_uint64]),
@@ -200,6 +201,20 @@ def su2_polyakov(lat, out=None, corr=None, with_corr=True, stream=None):
     _check(lib.su2_polyakov(lat.ref(), out.data_ptr(), corr.data_ptr() if corr is not None else None,
                             _stream(stream)))
     return out, corr
+
+
+def su2_measure(lat, plaq=None, poly=None, corr=None, with_corr=True, stream=None):
+    """Enqueue plaquette and Polyakov loop in one pass; returns (plaq, poly,
+    corr) device tensors laid out as su2_plaquette's and su2_polyakov's."""
+    if plaq is None:
+        plaq = torch.empty(7, dtype=torch.float64, device=lat.device)
+    if poly is None:
+        poly = torch.empty(2, dtype=torch.float64, device=lat.device)
+    if corr is None and with_corr:
+        corr = torch.empty(max(1, min(lat.n[:3]) // 2), dtype=torch.float64, device=lat.device)
+    _check(lib.su2_measure(lat.ref(), plaq.data_ptr(), poly.data_ptr(),
+                           corr.data_ptr() if corr is not None else None, _stream(stream)))
+    return plaq, poly, corr
 
 
 def su2_get_flags(lat, out=None, stream=None):

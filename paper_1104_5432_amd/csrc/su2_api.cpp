@@ -170,6 +170,9 @@ WorkLayout work_layout(const int32_t n[4])
     off += round256((uint64_t)w.nblk_corr * (uint64_t)(w.rmax > 0 ? w.rmax : 1) * sizeof(double));
     w.off_lfield = off;
     off += round256(vs * sizeof(double));
+    w.nblk_meas = (uint32_t)((vs + 255) / 256); // one block per 256 spatial sites
+    w.off_meas = off;
+    off += round256((uint64_t)w.nblk_meas * 8 * sizeof(double));
     w.total = off;
     return w;
 }
@@ -296,6 +299,21 @@ int su2_polyakov(const su2_lattice_t *lat, double *d_out, double *d_corr, void *
     if (!aligned(d_out, 8) || (d_corr && !aligned(d_corr, 8)))
         return fail(SU2_EALIGN, "d_out and d_corr must be 8-byte aligned");
     su2::launch_polyakov(a, w, d_out, d_corr, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_measure(const su2_lattice_t *lat, double *d_plaq, double *d_poly, double *d_corr, void *stream)
+{
+    su2::LaunchArgs a;
+    su2::WorkLayout w;
+    int rc = check_lattice(lat, &a, &w);
+    if (rc)
+        return rc;
+    if (!d_plaq || !d_poly)
+        return fail(SU2_EINVAL, "d_plaq and d_poly must be device pointers to 7 and 2 doubles");
+    if (!aligned(d_plaq, 8) || !aligned(d_poly, 8) || (d_corr && !aligned(d_corr, 8)))
+        return fail(SU2_EALIGN, "d_plaq, d_poly and d_corr must be 8-byte aligned");
+    su2::launch_measure(a, w, d_plaq, d_poly, d_corr, (hipStream_t)stream);
     return launched();
 }
 

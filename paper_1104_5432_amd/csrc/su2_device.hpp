@@ -230,14 +230,6 @@ __host__ inline int default_strip(const int32_t n[4])
     return (int)w;
 }
 
-// Row ranges per column: tile_y > 0 as given (it divides Ny; the caller
-// checked), 0 = default (1).
-__host__ inline int default_ysplit(const int32_t n[4])
-{
-    (void)n;
-    return 1;
-}
-
 __host__ inline BlockOrder make_block_order(const int32_t n[4], int tile, int tile_y)
 {
     BlockOrder o = {};
@@ -248,7 +240,9 @@ __host__ inline BlockOrder make_block_order(const int32_t n[4], int tile, int ti
     const int w = tile == 0 ? default_strip(n) : tile;
     o.strip = w > 0 ? (uint32_t)w : 0u;
     o.div_w = make_fastdiv(w > 0 ? (uint32_t)w : 1u);
-    const int s = w > 0 ? (tile_y > 0 ? tile_y : default_ysplit(n)) : 1;
+    // row ranges per column: tile_y > 0 as given (it divides Ny; the caller
+    // checked), 0 = whole columns; plain order has none
+    const int s = (w > 0 && tile_y > 0) ? tile_y : 1;
     o.ysplit = (uint32_t)s;
     o.seg = o.cols / o.ysplit;
     o.div_seg = make_fastdiv(o.seg);

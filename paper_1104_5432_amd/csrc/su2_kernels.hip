@@ -287,7 +287,7 @@ __device__ __forceinline__ void overrelax_body(const Links<T> &U, const Geom &g,
 // Kernels: one lattice, or a batch of lattices in one launch.  A batch is a
 // device table of BatchEntry (geometry, links, beta, lattice id, flags and
 // the lattice's range of blocks, a multiple of 8 so that every lattice keeps
-// its XCD-aligned walk); a block finds its lattice by a scan of the table.
+// its XCD-aligned walk); a block looks its lattice up in the table.
 // The heat-bath sweep index is read from device memory when `d_sweep` is
 // given, so a captured graph can be replayed sweep after sweep.
 // ---------------------------------------------------------------------------

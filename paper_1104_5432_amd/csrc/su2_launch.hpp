@@ -13,8 +13,8 @@ constexpr int kF32 = 1;
 // Workspace layout: the flags word, then the reduction partials and the
 // Polyakov-loop field, each region 256-byte aligned.
 struct WorkLayout {
-    uint64_t off_plaq, off_poly, off_corr, off_lfield, total;
-    uint32_t nblk_plaq, nblk_poly, nblk_corr;
+    uint64_t off_plaq, off_poly, off_corr, off_lfield, off_meas, total;
+    uint32_t nblk_plaq, nblk_poly, nblk_corr, nblk_meas;
     int rmax;
 };
 
@@ -47,6 +47,8 @@ void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st);
 void launch_overrelax(const LaunchArgs &a, int mu, int par, hipStream_t st);
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st);
+void launch_measure(const LaunchArgs &a, const WorkLayout &w, double *d_plaq, double *d_poly, double *d_corr,
+                    hipStream_t st);
 void launch_get_flags(const LaunchArgs &a, uint32_t *d_flags, hipStream_t st);
 
 } // namespace su2

@@ -105,6 +105,80 @@ __global__ __launch_bounds__(kBlock) void plaquette_kernel(Links<T> U, Geom g, d
             partials[(size_t)j * gridDim.x + blockIdx.x] = acc[j];
 }
 
+// Plaquettes and Polyakov loop in one pass: a thread takes one spatial site
+// and walks t = 0..Nt-1.  At each t it loads the site's four links and the
+// nine links at x+e_x, x+e_y, x+e_z that the spatial plaquettes (01, 02, 12)
+// and the temporal ones need; the temporal plaquettes (mu, 3) of slice t-1
+// take U_mu(x + e_t) from the links just loaded for slice t (slice 0's links
+// close the last slice), and the Polyakov line multiplies U_3(x,t) in t
+// order.  13 loads per site instead of 16, every link read once as its own.
+// Partials per block, column by column: the six planes, sum L, sum |L|.
+template <class T>
+__global__ __launch_bounds__(kBlock) void measure_kernel(Links<T> U, Geom g, double *Lfield, double *partials)
+{
+    __shared__ double lds[kBlock / 64][8];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t sp = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (sp < g.vs) {
+        const uint32_t nx = (uint32_t)g.n[0], ny = (uint32_t)g.n[1], nz = (uint32_t)g.n[2];
+        const uint32_t yz = fdiv(sp, g.div_nx);
+        const uint32_t x = sp - yz * nx;
+        const uint32_t z = fdiv(yz, g.div_ny);
+        const uint32_t y = yz - z * ny;
+        // spatial site indices of the three forward neighbours
+        const uint32_t sx = (x + 1u == nx ? 0u : x + 1u) + nx * yz;
+        const uint32_t sy = x + nx * ((y + 1u == ny ? 0u : y + 1u) + ny * z);
+        const uint32_t sz = x + nx * (y + ny * (z + 1u == nz ? 0u : z + 1u));
+        const uint32_t par0 = (x + y + z) & 1u;
+        Quat<T> first[3], prev[4], prev3[3];
+        Quat<T> P = {1, 0, 0, 0};
+        for (uint32_t t = 0; t < (uint32_t)g.n[3]; ++t) {
+            const uint32_t base = g.vs * t;
+            const int par = (int)((par0 + t) & 1u), opp = par ^ 1;
+            const uint32_t cb = (base + sp) >> 1, cbx = (base + sx) >> 1, cby = (base + sy) >> 1,
+                           cbz = (base + sz) >> 1;
+            Quat<T> u[4];
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+                u[mu] = U.ld(mu, par, cb);
+            const Quat<T> x1 = U.ld(1, opp, cbx), x2 = U.ld(2, opp, cbx), x3 = U.ld(3, opp, cbx);
+            const Quat<T> y0 = U.ld(0, opp, cby), y2 = U.ld(2, opp, cby), y3 = U.ld(3, opp, cby);
+            const Quat<T> z0 = U.ld(0, opp, cbz), z1 = U.ld(1, opp, cbz), z3 = U.ld(3, opp, cbz);
+            acc[0] += (double)qdot(qmul(u[0], x1), qmul(u[1], y0)); // 01
+            acc[1] += (double)qdot(qmul(u[0], x2), qmul(u[2], z0)); // 02
+            acc[3] += (double)qdot(qmul(u[1], y2), qmul(u[2], z1)); // 12
+            if (t == 0) {
+#pragma unroll
+                for (int mu = 0; mu < 3; ++mu)
+                    first[mu] = u[mu];
+            } else {
+                acc[2] += (double)qdot(qmul(prev[0], prev3[0]), qmul(prev[3], u[0])); // 03 at t-1
+                acc[4] += (double)qdot(qmul(prev[1], prev3[1]), qmul(prev[3], u[1])); // 13
+                acc[5] += (double)qdot(qmul(prev[2], prev3[2]), qmul(prev[3], u[2])); // 23
+            }
+            P = qmul(P, u[3]);
+#pragma unroll
+            for (int mu = 0; mu < 4; ++mu)
+                prev[mu] = u[mu];
+            prev3[0] = x3;
+            prev3[1] = y3;
+            prev3[2] = z3;
+        }
+        acc[2] += (double)qdot(qmul(prev[0], prev3[0]), qmul(prev[3], first[0]));
+        acc[4] += (double)qdot(qmul(prev[1], prev3[1]), qmul(prev[3], first[1]));
+        acc[5] += (double)qdot(qmul(prev[2], prev3[2]), qmul(prev[3], first[2]));
+        const double L = (double)P.w;
+        Lfield[sp] = L;
+        acc[6] = L;
+        acc[7] = fabs(L);
+    }
+    block_sum<8>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            partials[(size_t)j * gridDim.x + blockIdx.x] = acc[j];
+}
+
 // Polyakov loop at each spatial site: ordered product of the Nt temporal links.
 template <class T>
 __global__ __launch_bounds__(kBlock) void polyakov_kernel(Links<T> U, Geom g, double *Lfield, double *partials)
@@ -230,6 +304,26 @@ void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, do
     else
         polyakov_kernel<double><<<w.nblk_poly, kBlock, 0, st>>>(links_of<double>(a), g, Lf, pp);
     colsum_kernel<<<2, kBlock, 0, st>>>(pp, w.nblk_poly, 1.0 / (double)g.vs, d_out);
+    if (d_corr && w.rmax > 0) {
+        double *cp = reinterpret_cast<double *>(a.work + w.off_corr);
+        polycorr_kernel<<<dim3(w.nblk_corr, (uint32_t)w.rmax), kBlock, 0, st>>>(Lf, g, cp);
+        colsum_kernel<<<w.rmax, kBlock, 0, st>>>(cp, w.nblk_corr, 1.0 / (3.0 * (double)g.vs), d_corr);
+    }
+}
+
+void launch_measure(const LaunchArgs &a, const WorkLayout &w, double *d_plaq, double *d_poly, double *d_corr,
+                    hipStream_t st)
+{
+    const Geom g = make_geom(a.n, a.tile, a.tile_y);
+    double *Lf = reinterpret_cast<double *>(a.work + w.off_lfield);
+    double *pm = reinterpret_cast<double *>(a.work + w.off_meas);
+    if (a.prec == kF32)
+        measure_kernel<float><<<w.nblk_meas, kBlock, 0, st>>>(links_of<float>(a), g, Lf, pm);
+    else
+        measure_kernel<double><<<w.nblk_meas, kBlock, 0, st>>>(links_of<double>(a), g, Lf, pm);
+    colsum_kernel<<<6, kBlock, 0, st>>>(pm, w.nblk_meas, 1.0 / (double)a.volume, d_plaq + 1);
+    plaq_total_kernel<<<1, 64, 0, st>>>(d_plaq);
+    colsum_kernel<<<2, kBlock, 0, st>>>(pm + (size_t)6 * w.nblk_meas, w.nblk_meas, 1.0 / (double)g.vs, d_poly);
     if (d_corr && w.rmax > 0) {
         double *cp = reinterpret_cast<double *>(a.work + w.off_corr);
         polycorr_kernel<<<dim3(w.nblk_corr, (uint32_t)w.rmax), kBlock, 0, st>>>(Lf, g, cp);

@@ -277,6 +277,36 @@ def test_observables_match_oracle(su2, n, prec):
     assert _maxdiff(corr.cpu().numpy()[:len(C)], C) <= tol
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", SHAPES + [(16, 8, 8, 4)])
+def test_single_pass_measurement_matches_oracle(su2, n, prec):
+    # su2_measure: plaquette planes, Polyakov loop and correlator in one pass
+    U0 = oracle.init_hot(n, 62)
+    for s in range(3):
+        oracle.heatbath_sweep(n, U0, 2.4, 62, s)
+    lat = _lat(su2, n, prec, U0)
+    Uc = su2.to_canonical(lat).numpy()
+    plaq, poly, corr = su2.su2_measure(lat)
+    plaq_sep = su2.su2_plaquette(lat)
+    poly_sep, corr_sep = su2.su2_polyakov(lat)
+    _sync()
+    p, planes = oracle.plaquette(n, Uc)
+    l_mean, l_abs = oracle.polyakov(n, Uc)
+    C = oracle.polyakov_corr(n, Uc)
+    tol = 1e-13 if prec == "f64" else 2e-6
+    g = plaq.cpu().numpy()
+    assert abs(g[0] - p) <= tol and np.max(np.abs(g[1:] - planes)) <= tol
+    g = poly.cpu().numpy()
+    assert abs(g[0] - l_mean) <= tol and abs(g[1] - l_abs) <= tol
+    assert _maxdiff(corr.cpu().numpy()[:len(C)], C) <= tol
+    # against the separate calls (same quantities; FP64 agrees to the
+    # summation order, FP32 to the rounding of the FP32 products)
+    tol_sep = 1e-14 if prec == "f64" else 2e-6
+    assert _maxdiff(plaq.cpu().numpy(), plaq_sep.cpu().numpy()) <= tol_sep
+    assert _maxdiff(poly.cpu().numpy(), poly_sep.cpu().numpy()) <= tol_sep
+    assert _maxdiff(corr.cpu().numpy(), corr_sep.cpu().numpy()) <= tol_sep
+
+
 def test_observables_gauge_invariant_on_gpu(su2):
     n = (8, 6, 4, 6)
     U0 = oracle.init_hot(n, 17)
