@@ -9,7 +9,9 @@ sweep on a scratch lattice (hot start, never the caller's lattice) after a
 warm-up, timed with HIP events on the current stream; the fastest total
 wins.  The walk changes no result, only the order in which blocks visit the
 lattice, so tuning is safe to apply to any chain.  Choices are cached in a
-JSON file keyed by device architecture, CU count, extents and precision.
+JSON file keyed by device architecture, CU count, extents and precision; a
+table shipped with the package (tuned_walks.json, measured on an MI355X)
+answers for the benchmarked lattices before anything is timed.
 """
 import json
 import os
@@ -21,6 +23,9 @@ from . import (Lattice, su2_heatbath_sweep, su2_init_hot, su2_overrelax)
 # The cache file: $SU2_AUTOTUNE_CACHE, else ~/.cache/su2_mi355x/tiles.json.
 DEFAULT_CACHE = os.environ.get("SU2_AUTOTUNE_CACHE") or os.path.join(
     os.path.expanduser("~"), ".cache", "su2_mi355x", "tiles.json")
+# Walks measured on an MI355X for the benchmarked lattices (same key format);
+# consulted after the cache and before any timing.
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_walks.json")
 
 
 def candidates(n):
@@ -40,8 +45,12 @@ def _key(n, prec, device):
     # architecture and CU count: the marketing name can differ between
     # processes on the same device (e.g. under a profiler)
     p = torch.cuda.get_device_properties(torch.device(device))
-    arch = getattr(p, "gcnArchName", "") or p.name
-    return f"{arch}|{p.multi_processor_count}cu|{'x'.join(str(int(v)) for v in n)}|{prec}"
+    arch = (getattr(p, "gcnArchName", "") or p.name).split(":")[0]
+    return key_for(arch, p.multi_processor_count, n, prec)
+
+
+def key_for(arch, cus, n, prec):
+    return f"{arch}|{int(cus)}cu|{'x'.join(str(int(v)) for v in n)}|{prec}"
 
 
 def _load(path):
@@ -77,9 +86,10 @@ def tune(n, prec="f32", device="cuda", cache=DEFAULT_CACHE, reps=3, refresh=Fals
     """Return the fastest walk (tile, tile_y) for extents n (and store it in
     the cache)."""
     key = _key(n, prec, device)
-    table = _load(cache) if cache else {}
-    if not refresh and key in table and "tile_y" in table[key]:
-        return int(table[key]["tile"]), int(table[key]["tile_y"])
+    if not refresh:
+        for table in (_load(cache) if cache else {}, _load(SHIPPED)):
+            if key in table and "tile_y" in table[key]:
+                return int(table[key]["tile"]), int(table[key]["tile_y"])
     cands = candidates(n)
     if max_candidates is not None:
         cands = cands[:max_candidates]

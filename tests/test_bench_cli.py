@@ -39,3 +39,17 @@ def test_stored_traffic_lookup_matches_walk_and_sources(tmp_path, monkeypatch):
     assert bench.profiled_traffic("heatbath_kernel", "f32", "8,8,8,8", (2, 1)) is None
     monkeypatch.setattr(bench, "csrc_sha256", lambda: "0" * 64)
     assert bench.profiled_traffic("overrelax_kernel", "f32", "8,8,8,8", (2, 1)) is None
+
+
+def test_shipped_walks_are_valid_candidates():
+    import json
+    path = os.path.join(ROOT, "paper_1104_5432_amd", "tuned_walks.json")
+    with open(path) as f:
+        table = json.load(f)
+    assert table
+    for key, v in table.items():
+        arch, cus, shape, prec = key.split("|")
+        n = tuple(int(x) for x in shape.split("x"))
+        assert arch.startswith("gfx") and cus.endswith("cu") and prec in ("f32", "f64")
+        assert v["tile"] == -1 or n[2] % v["tile"] == 0
+        assert v["tile_y"] == 0 or n[1] % v["tile_y"] == 0

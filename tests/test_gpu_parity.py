@@ -509,6 +509,8 @@ def test_autotuner_picks_a_valid_walk(su2, tmp_path):
     walk = autotune.tune(n, "f32", cache=cache, reps=2)
     assert walk in autotune.candidates(n)
     assert autotune.tune(n, "f32", cache=cache) == walk          # cached
+    # the shipped table answers for the benchmarked lattice on this device
+    assert autotune._key((64, 64, 64, 64), "f32", "cuda") in autotune._load(autotune.SHIPPED)
     # the tuned walk changes no result
     a = su2.Lattice(n, "f32", device="cuda", tile=walk[0], tile_y=walk[1])
     b = su2.Lattice(n, "f32", device="cuda", tile=-1)
