@@ -2,8 +2,9 @@
 
 One step = one pass of the whole path on a resident lattice: 1 heat-bath
 sweep (8 checkerboard launches) + 4 overrelaxation sweeps (32 launches) +
-mean plaquette, Polyakov loop and its on-axis correlator (one measurement
-pass over the links, su2_measure).  Default workload:
+mean plaquette (taken by the last overrelaxation sweep from the staples it
+forms, su2_overrelax_measured), Polyakov loop and its on-axis correlator
+(su2_polyakov).  Default workload:
 64^4 periodic lattice, beta = 2.3, FP32 links, hot start (Philox seed 1234).
 The value counts 20 V link updates per step (4 V heat bath + 16 V
 overrelaxation); the per-kernel roofline uses the algorithmic bytes of each
@@ -56,6 +57,9 @@ def parse():
                     help="single: one lattice (--shape); scan: 16 lattices mixing 32^3x4, 48^3x6, "
                          "64^3x8 at beta 2.2..2.7, one captured graph replay per sweep; learned: the "
                          "learned block proposal at 16^3x4; precision: FP32 against FP64 observables")
+    ap.add_argument("--fused-plaquette", action=argparse.BooleanOptionalAction, default=True,
+                    help="take the plaquette in the last sweep of the step (no separate pass); "
+                         "--no-fused-plaquette measures it with the one-pass measurement kernel")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="bytes of a plain device copy to run before the timed region "
                          "(reference for hardware byte counters)")
@@ -389,17 +393,35 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # With the fused plaquette the last sweep of the step measures it and
+    # the Polyakov pass follows; the overrelaxation events bracket only the
+    # plain sweeps before that last one (the kernel the roofline reports),
+    # unless the step has a single overrelaxation sweep.
+    fused = args.fused_plaquette
+    or_plain = args.or_per_hb - 1 if fused and args.or_per_hb >= 2 else args.or_per_hb
+
     def step(s, ev=None):
+        k = s - args.warmup if s >= args.warmup else 0
         if ev:
             ev[0].record(stream)
-        su2.su2_heatbath_sweep(lat, args.beta, args.seed, s)
+        if fused and args.or_per_hb == 0:
+            su2.su2_heatbath_sweep_measured(lat, args.beta, args.seed, s, plaq[k])
+        else:
+            su2.su2_heatbath_sweep(lat, args.beta, args.seed, s)
         if ev:
             ev[1].record(stream)
-        su2.su2_overrelax(lat, args.or_per_hb)
+        if fused and args.or_per_hb == 1:
+            su2.su2_overrelax_measured(lat, 1, plaq[k])
+        elif or_plain:
+            su2.su2_overrelax(lat, or_plain)
         if ev:
             ev[2].record(stream)
-        k = s - args.warmup if s >= args.warmup else 0
-        su2.su2_measure(lat, plaq[k], poly[k], corr[k])     # plaquette, Polyakov loop, correlator
+        if not fused:
+            su2.su2_measure(lat, plaq[k], poly[k], corr[k])     # plaquette, Polyakov loop, correlator
+            return
+        if args.or_per_hb >= 2:
+            su2.su2_overrelax_measured(lat, 1, plaq[k])
+        su2.su2_polyakov(lat, poly[k], corr[k])
 
     for s in range(args.warmup):
         step(s)
@@ -427,7 +449,7 @@ def main():
 
     link_b = 16 if args.prec == "f32" else 32
     half = vol // 2
-    or_launch_ms = or_ms / (8 * args.or_per_hb) if args.or_per_hb else float("nan")
+    or_launch_ms = or_ms / (8 * or_plain) if or_plain else float("nan")
     hb_launch_ms = hb_ms / 8
     or_bytes = half * 9 * link_b          # algorithmic bytes per overrelaxation launch
     hb_bytes = half * 8 * link_b          # algorithmic bytes per heat-bath launch
@@ -469,20 +491,22 @@ def main():
             "workload": f"SU(2) pure gauge {'^'.join([str(n[0]), '4']) if len(set(n)) == 1 else 'x'.join(map(str, n))} "
                         f"periodic, beta={args.beta}, {args.start} start (Philox seed {args.seed}), "
                         f"{args.prec.upper()} links, per step 1 heat-bath + {args.or_per_hb} overrelaxation "
-                        f"sweeps + FP64 plaquette + Polyakov loop/correlator",
+                        f"sweeps + FP64 plaquette ({'taken by the last sweep' if fused else 'measurement pass'}) "
+                        f"+ Polyakov loop/correlator",
             "lattice": list(n),
             "beta": args.beta,
             "or_per_hb": args.or_per_hb,
             "tile": tile,
             "tile_y": tile_y,
             "start": args.start,
+            "fused_plaquette": fused,
             "link_updates_per_step": updates,
         },
         # the dominant kernel: overrelaxation when the step has any, else heat bath
         "roofline": dict(or_roof if args.or_per_hb else hb_roof, bound="hbm", peak=HBM_PEAK_GBS, unit="GB/s"),
         "heatbath_roofline": hb_roof,
         "overrelax_roofline": or_roof if args.or_per_hb else None,
-        "sweep_roofline_frac": ((hb_bytes * 8 + or_bytes * 8 * args.or_per_hb) / ((hb_ms + or_ms) * 1e-3) / 1e9)
+        "sweep_roofline_frac": ((hb_bytes * 8 + or_bytes * 8 * or_plain) / ((hb_ms + or_ms) * 1e-3) / 1e9)
                                / HBM_PEAK_GBS,
         "wall_s_timed": wall,
         "check": {"plaquette_last": last_plaq, "polyakov_abs_last": last_poly, "flags": flags},

@@ -145,6 +145,25 @@ int su2_plaquette(const su2_lattice_t *lat, double *d_out, void *stream);
  * r = 1..R.  FP64 sums, fixed reduction order. */
 int su2_polyakov(const su2_lattice_t *lat, double *d_out, double *d_corr, void *stream);
 
+/* A heat-bath sweep (as su2_heatbath_sweep) that also leaves the mean
+ * plaquette of the configuration it produces in d_plaq (device, 7 doubles,
+ * as su2_plaquette's d_out; Sec. 2.1 measures it after every iteration).
+ * No extra pass over the lattice: in class (mu, odd), mu >= 1, every link of
+ * the plaquettes of planes (nu, mu), nu < mu, is final, and each such
+ * plaquette holds exactly one odd mu-link, so the classes (1,odd), (2,odd),
+ * (3,odd) take the half traces of their new links with the staple products
+ * they already formed (FP64 from the half trace on).  The links are
+ * bitwise those of su2_heatbath_sweep; the plaquette agrees with
+ * su2_plaquette to the summation order (FP64) or to the rounding of FP32
+ * products (FP32). */
+int su2_heatbath_sweep_measured(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t sweep,
+                                double *d_plaq, void *stream);
+
+/* su2_overrelax with the mean plaquette of the final configuration left in
+ * d_plaq, measured by the last sweep as in su2_heatbath_sweep_measured
+ * (n_sweeps = 0: su2_plaquette of the current configuration). */
+int su2_overrelax_measured(const su2_lattice_t *lat, int32_t n_sweeps, double *d_plaq, void *stream);
+
 /* Both measurements of a configuration in one pass over the links (Sec. 2.1
  * mean plaquette; Sec. 2.2 eqs. (1), (3)): d_plaq (device, 7 doubles) as
  * su2_plaquette's d_out, d_poly (device, 2 doubles) as su2_polyakov's d_out,

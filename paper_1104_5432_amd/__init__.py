@@ -62,6 +62,9 @@ _SIGNATURES = {
     "su2_plaquette": (ctypes.c_int, [_LP, _VP, _VP]),
     "su2_polyakov": (ctypes.c_int, [_LP, _VP, _VP, _VP]),
     "su2_measure": (ctypes.c_int, [_LP, _VP, _VP, _VP, _VP]),
+    "su2_heatbath_sweep_measured": (ctypes.c_int, [_LP, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, _VP,
+                                                   _VP]),
+    "su2_overrelax_measured": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, _VP]),
     "su2_get_flags": (ctypes.c_int, [_LP, _VP, _VP]),
     "su2_batch_table_bytes": (ctypes.c_uint64, [ctypes.c_int32]),
     "su2_batch_fill": (ctypes.c_int, [_LP, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, _VP, ctypes.c_uint64]),
@@ -201,6 +204,25 @@ def su2_polyakov(lat, out=None, corr=None, with_corr=True, stream=None):
     _check(lib.su2_polyakov(lat.ref(), out.data_ptr(), corr.data_ptr() if corr is not None else None,
                             _stream(stream)))
     return out, corr
+
+
+def su2_heatbath_sweep_measured(lat, beta, seed, sweep, plaq=None, stream=None):
+    """Heat-bath sweep that also leaves the plaquette (7 float64, as
+    su2_plaquette) of the configuration it produces; returns that tensor."""
+    if plaq is None:
+        plaq = torch.empty(7, dtype=torch.float64, device=lat.device)
+    _check(lib.su2_heatbath_sweep_measured(lat.ref(), float(beta), int(seed), int(sweep), plaq.data_ptr(),
+                                           _stream(stream)))
+    return plaq
+
+
+def su2_overrelax_measured(lat, n_sweeps=1, plaq=None, stream=None):
+    """Overrelaxation sweeps whose last one leaves the plaquette of the final
+    configuration; returns that tensor (7 float64)."""
+    if plaq is None:
+        plaq = torch.empty(7, dtype=torch.float64, device=lat.device)
+    _check(lib.su2_overrelax_measured(lat.ref(), int(n_sweeps), plaq.data_ptr(), _stream(stream)))
+    return plaq
 
 
 def su2_measure(lat, plaq=None, poly=None, corr=None, with_corr=True, stream=None):

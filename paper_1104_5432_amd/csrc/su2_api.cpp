@@ -227,7 +227,7 @@ int su2_heatbath_halfsweep(const su2_lattice_t *lat, double beta, uint64_t seed,
         rc = check_class(mu, parity);
     if (rc)
         return rc;
-    su2::launch_heatbath(a, beta, seed, sweep, nullptr, mu, parity, (hipStream_t)stream);
+    su2::launch_heatbath(a, beta, seed, sweep, nullptr, mu, parity, nullptr, (hipStream_t)stream);
     return launched();
 }
 
@@ -241,7 +241,7 @@ int su2_heatbath_sweep(const su2_lattice_t *lat, double beta, uint64_t seed, uin
         return rc;
     for (int mu = 0; mu < 4; ++mu)
         for (int p = 0; p < 2; ++p)
-            su2::launch_heatbath(a, beta, seed, sweep, nullptr, mu, p, (hipStream_t)stream);
+            su2::launch_heatbath(a, beta, seed, sweep, nullptr, mu, p, nullptr, (hipStream_t)stream);
     return launched();
 }
 
@@ -253,7 +253,7 @@ int su2_overrelax_halfsweep(const su2_lattice_t *lat, int32_t mu, int32_t parity
         rc = check_class(mu, parity);
     if (rc)
         return rc;
-    su2::launch_overrelax(a, mu, parity, (hipStream_t)stream);
+    su2::launch_overrelax(a, mu, parity, nullptr, (hipStream_t)stream);
     return launched();
 }
 
@@ -268,7 +268,71 @@ int su2_overrelax(const su2_lattice_t *lat, int32_t n_sweeps, void *stream)
     for (int s = 0; s < n_sweeps; ++s)
         for (int mu = 0; mu < 4; ++mu)
             for (int p = 0; p < 2; ++p)
-                su2::launch_overrelax(a, mu, p, (hipStream_t)stream);
+                su2::launch_overrelax(a, mu, p, nullptr, (hipStream_t)stream);
+    return launched();
+}
+
+namespace {
+
+int check_plaq_out(const double *d_plaq)
+{
+    if (!d_plaq)
+        return fail(SU2_EINVAL, "d_plaq must be a device pointer to 7 doubles");
+    if (!aligned(d_plaq, 8))
+        return fail(SU2_EALIGN, "d_plaq must be 8-byte aligned");
+    return SU2_OK;
+}
+
+// The plaquette-partials region when class (mu, p) of the last sweep writes
+// plane partials, else null.
+double *plaq_region(const su2::LaunchArgs &a, const su2::WorkLayout &w, int mu, int p)
+{
+    return (p == 1 && mu >= 1) ? reinterpret_cast<double *>(a.work + w.off_plaq) : nullptr;
+}
+
+}
+
+int su2_heatbath_sweep_measured(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t sweep,
+                                double *d_plaq, void *stream)
+{
+    su2::LaunchArgs a;
+    su2::WorkLayout w;
+    int rc = check_lattice(lat, &a, &w);
+    if (!rc)
+        rc = check_beta(beta);
+    if (!rc)
+        rc = check_plaq_out(d_plaq);
+    if (rc)
+        return rc;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int p = 0; p < 2; ++p)
+            su2::launch_heatbath(a, beta, seed, sweep, nullptr, mu, p, plaq_region(a, w, mu, p),
+                                 (hipStream_t)stream);
+    su2::launch_plaquette_sum(a, w, d_plaq, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_overrelax_measured(const su2_lattice_t *lat, int32_t n_sweeps, double *d_plaq, void *stream)
+{
+    su2::LaunchArgs a;
+    su2::WorkLayout w;
+    int rc = check_lattice(lat, &a, &w);
+    if (!rc)
+        rc = check_plaq_out(d_plaq);
+    if (rc)
+        return rc;
+    if (n_sweeps < 0)
+        return fail(SU2_EINVAL, "n_sweeps must be >= 0");
+    if (n_sweeps == 0) {
+        su2::launch_plaquette(a, w, d_plaq, (hipStream_t)stream);
+        return launched();
+    }
+    for (int s = 0; s < n_sweeps; ++s)
+        for (int mu = 0; mu < 4; ++mu)
+            for (int p = 0; p < 2; ++p)
+                su2::launch_overrelax(a, mu, p, s + 1 == n_sweeps ? plaq_region(a, w, mu, p) : nullptr,
+                                      (hipStream_t)stream);
+    su2::launch_plaquette_sum(a, w, d_plaq, (hipStream_t)stream);
     return launched();
 }
 

@@ -613,8 +613,17 @@ __device__ __forceinline__ ColAddr col_addr(const Geom &g, uint32_t i, int par)
 // so that the link's local action is -(beta/2) Tr(U_mu(x) V).  The order of
 // the products and sums is the same for both addressing policies.
 // ---------------------------------------------------------------------------
-template <class T, int MU, class A>
-__device__ __forceinline__ Quat<T> staple(const Links<T> &U, const A &ad, int par)
+// The sum of the two staple products of plane (nu, MU), nu < MU: the half
+// trace is linear, so its half trace with U_MU(x) is the sum of the two
+// plaquettes of that plane containing the link.  Recorded when the update
+// also measures the plaquette.
+template <class T>
+struct PlaneTerms {
+    Quat<T> s[3];
+};
+
+template <class T, int MU, bool TERMS, class A>
+__device__ __forceinline__ Quat<T> staple_impl(const Links<T> &U, const A &ad, int par, PlaneTerms<T> *terms)
 {
     const int opp = par ^ 1;
     const int32_t m0 = (MU == 0), m1 = (MU == 1), m2 = (MU == 2), m3 = (MU == 3);
@@ -633,14 +642,39 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const A &ad, int pa
         const Quat<T> a = ad.ld(U, nu, opp, i_xp);
         const Quat<T> b = ad.ld(U, MU, opp, i_xpn);
         const Quat<T> c = ad.ld(U, nu, par, i_x);
-        qacc(V, qmul_nd(qmul_nd(a, b), c));
+        const Quat<T> su = qmul_nd(qmul_nd(a, b), c);
+        qacc(V, su);
         // lower staple
         const Quat<T> d = ad.ld(U, nu, par, i_xpmn);
         const Quat<T> e = ad.ld(U, MU, opp, i_xmn);
         const Quat<T> f = ad.ld(U, nu, opp, i_xmn);
-        qacc(V, qmul(qmul_dd(d, e), f));
+        const Quat<T> sl = qmul(qmul_dd(d, e), f);
+        qacc(V, sl);
+        if constexpr (TERMS) {
+            if (nu < MU)
+                terms->s[nu] = {su.w + sl.w, su.x + sl.x, su.y + sl.y, su.z + sl.z};
+        }
     }
     return V;
+}
+
+template <class T, int MU, class A>
+__device__ __forceinline__ Quat<T> staple(const Links<T> &U, const A &ad, int par)
+{
+    return staple_impl<T, MU, false>(U, ad, par, nullptr);
+}
+
+// (1/2) Tr(U W) for unit quaternions: the scalar part of the product.
+template <class T>
+__device__ __forceinline__ T half_trace(const Quat<T> &u, const Quat<T> &w)
+{
+    return u.w * w.w - u.x * w.x - u.y * w.y - u.z * w.z;
+}
+
+// Index of plane (nu, mu), nu < mu, in the order 01, 02, 03, 12, 13, 23.
+__host__ __device__ constexpr int plane_index(int nu, int mu)
+{
+    return nu * (7 - nu) / 2 + (mu - nu - 1);
 }
 
 // The staple from a site's coordinates (any geometry).
@@ -674,6 +708,42 @@ __device__ __forceinline__ void reserve_lds_for_residency()
     __shared__ volatile char reservation[kOrResidencyLds];
     if (threadIdx.x == kBlock) // never true: keeps the reservation allocated
         reservation[0] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions: wave64 shuffles, then an LDS tree over the
+// block's waves in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum NV values over the block; thread 0 returns the totals.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[NV])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        v[j] = wave_sum(v[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            lds[wave][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w)
+                s += lds[w][j];
+            v[j] = s;
+        }
+    }
 }
 
 } // namespace su2

@@ -138,10 +138,35 @@ struct Direction<float> {
 // ballots, no atomics) and retried by as few lanes as there are rejections,
 // so a wave64 no longer idles until its slowest lane accepts.  A link's
 // attempt sequence, and so its result, does not depend on which lane runs it.
-template <class T, int MU, bool COL>
+// Plaquette of the configuration a sweep leaves, from its last classes: in
+// class (MU, odd) every link of the plaquettes of planes (nu, MU), nu < MU,
+// is final, and each of those plaquettes holds exactly one odd MU-link, so
+// classes (1,odd), (2,odd), (3,odd) of the last sweep count all six planes
+// once.  Each thread takes (1/2)Tr of the new link with the recorded sum of
+// the two staple products of each such plane (FP64 from the half trace on,
+// as in the plaquette kernel) and the block writes one partial per plane.
+template <class T, int MU>
+__device__ __forceinline__ void plaquette_partials(const Quat<T> &u, const PlaneTerms<T> &terms, bool valid,
+                                                   double *partials)
+{
+    constexpr int NP = MU > 0 ? MU : 1;
+    __shared__ double lds[kBlock / 64][NP];
+    double acc[NP];
+#pragma unroll
+    for (int nu = 0; nu < NP; ++nu)
+        acc[nu] = valid ? (double)half_trace(u, terms.s[nu]) : 0.0;
+    block_sum<NP>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int nu = 0; nu < NP; ++nu)
+            partials[(size_t)plane_index(nu, MU) * gridDim.x + blockIdx.x] = acc[nu];
+}
+
+template <class T, int MU, bool COL, bool PLAQ = false>
 __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, int par, double beta,
                                               uint32_t k0, uint32_t k1, uint32_t c1, uint32_t sweep,
-                                              uint32_t *flags, uint32_t b, uint32_t nblocks)
+                                              uint32_t *flags, uint32_t b, uint32_t nblocks,
+                                              double *plaq_partials = nullptr)
 {
     __shared__ uint32_t s_queue[kBlock];
     __shared__ uint32_t s_site[kBlock];
@@ -158,18 +183,22 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     Quat<T> Vh = {1, 0, 0, 0};
     double alpha = 0.0;
     bool need = false;
+    PlaneTerms<T> terms;
     if (valid) {
         Quat<T> V;
         if constexpr (COL) {
             const ColAddr ad = col_addr(g, i, par);
             own = ad.at(0, 0, 0, 0);
             site = ad.site();
-            V = staple<T, MU>(U, ad, par);
+            V = staple_impl<T, MU, PLAQ>(U, ad, par, &terms);
         } else {
             own = walk_cb(i, g.ord);
-            const Site s = site_of_cb(g, own, par);
-            site = s.site;
-            V = staple<T, MU>(U, g, s, own, par);
+            CbAddr ad;
+            ad.s = site_of_cb(g, own, par);
+            ad.cb = own;
+            ad.g = &g;
+            site = ad.s.site;
+            V = staple_impl<T, MU, PLAQ>(U, ad, par, &terms);
         }
         const T k = sqrt(V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z);
         if (!isfinite(k)) {
@@ -232,55 +261,73 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
         if (!ok)
             atomicOr(flags, kFlagCap);
     }
-    if (!ok)
-        return;
-    const Quat<T> X = Direction<T>::make(x0, xlen, philox(site, c1, sweep, 2u, k0, k1));
-    const Quat<T> Un = unitize(qmul_nd(X, Vh));
-    if constexpr (COL)
-        U.stb(MU, par, own, Un);
-    else
-        U.st(MU, par, own, Un);
+    Quat<T> Un = {1, 0, 0, 0};
+    if (ok) {
+        const Quat<T> X = Direction<T>::make(x0, xlen, philox(site, c1, sweep, 2u, k0, k1));
+        Un = unitize(qmul_nd(X, Vh));
+        if constexpr (COL)
+            U.stb(MU, par, own, Un);
+        else
+            U.st(MU, par, own, Un);
+    }
+    if constexpr (PLAQ && MU > 0) {
+        if (valid && !ok) // the link was kept
+            Un = COL ? U.ldb(MU, par, own) : U.ld(MU, par, own);
+        plaquette_partials<T, MU>(Un, terms, valid, plaq_partials);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Overrelaxation for one class: U -> Vhat^+ U^+ Vhat^+ = (Vhat U Vhat)^+.
 // ---------------------------------------------------------------------------
-template <class T, int MU, class A>
-__device__ __forceinline__ void overrelax_link(const Links<T> &U, const A &ad, int par, uint32_t *flags)
+template <class T, int MU, bool PLAQ, class A>
+__device__ __forceinline__ Quat<T> overrelax_link(const Links<T> &U, const A &ad, int par, uint32_t *flags,
+                                                  PlaneTerms<T> *terms)
 {
-    const Quat<T> V = staple<T, MU>(U, ad, par);
+    const Quat<T> V = staple_impl<T, MU, PLAQ>(U, ad, par, terms);
     const uint32_t own = ad.at(0, 0, 0, 0);
     const Quat<T> u = ad.ld_nt(U, MU, par, own); // read by this update only
     const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
     const T k = sqrt(k2);
     if (!isfinite(k)) {
         atomicOr(flags, kFlagNonFinite);
-        return;
+        return u;
     }
     if (k == T(0))
-        return;
+        return u;
     const T inv = T(1) / k;
     const Quat<T> Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
     const Quat<T> w = qmul(qmul(Vh, u), Vh);
-    ad.st(U, MU, par, own, unitize(Quat<T>{w.w, -w.x, -w.y, -w.z}));
+    const Quat<T> un = unitize(Quat<T>{w.w, -w.x, -w.y, -w.z});
+    ad.st(U, MU, par, own, un);
+    return un;
 }
 
-template <class T, int MU, bool COL>
+template <class T, int MU, bool COL, bool PLAQ = false>
 __device__ __forceinline__ void overrelax_body(const Links<T> &U, const Geom &g, int par, uint32_t *flags,
-                                               uint32_t b, uint32_t nblocks)
+                                               uint32_t b, uint32_t nblocks, double *plaq_partials = nullptr)
 {
     const uint32_t i = xcd_tile(b, nblocks) * kBlock + threadIdx.x;
-    if (i >= g.half)
-        return;
-    if constexpr (COL) {
-        overrelax_link<T, MU>(U, col_addr(g, i, par), par, flags);
-    } else {
-        CbAddr ad;
-        ad.cb = walk_cb(i, g.ord);
-        ad.s = site_of_cb(g, ad.cb, par);
-        ad.g = &g;
-        overrelax_link<T, MU>(U, ad, par, flags);
+    const bool valid = i < g.half;
+    if constexpr (!PLAQ) {
+        if (!valid)
+            return;
     }
+    PlaneTerms<T> terms;
+    Quat<T> un = {1, 0, 0, 0};
+    if (valid) {
+        if constexpr (COL) {
+            un = overrelax_link<T, MU, PLAQ>(U, col_addr(g, i, par), par, flags, &terms);
+        } else {
+            CbAddr ad;
+            ad.cb = walk_cb(i, g.ord);
+            ad.s = site_of_cb(g, ad.cb, par);
+            ad.g = &g;
+            un = overrelax_link<T, MU, PLAQ>(U, ad, par, flags, &terms);
+        }
+    }
+    if constexpr (PLAQ && MU > 0)
+        plaquette_partials<T, MU>(un, terms, valid, plaq_partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -291,22 +338,24 @@ __device__ __forceinline__ void overrelax_body(const Links<T> &U, const Geom &g,
 // The heat-bath sweep index is read from device memory when `d_sweep` is
 // given, so a captured graph can be replayed sweep after sweep.
 // ---------------------------------------------------------------------------
-template <class T, int MU, bool COL>
+template <class T, int MU, bool COL, bool PLAQ>
 __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, int par, double beta,
                                                            uint32_t k0, uint32_t k1, uint32_t c1,
                                                            uint32_t sweep, const uint32_t *d_sweep,
-                                                           uint32_t *flags)
+                                                           uint32_t *flags, double *plaq_partials)
 {
     const uint32_t sw = d_sweep ? *d_sweep : sweep;
-    heatbath_body<T, MU, COL>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x);
+    heatbath_body<T, MU, COL, PLAQ>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x,
+                                    plaq_partials);
 }
 
-template <class T, int MU, bool COL, bool CAP>
-__global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags)
+template <class T, int MU, bool COL, bool CAP, bool PLAQ>
+__global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, int par, uint32_t *flags,
+                                                            double *plaq_partials)
 {
     if constexpr (CAP)
         reserve_lds_for_residency();
-    overrelax_body<T, MU, COL>(U, g, par, flags, blockIdx.x, gridDim.x);
+    overrelax_body<T, MU, COL, PLAQ>(U, g, par, flags, blockIdx.x, gridDim.x, plaq_partials);
 }
 
 // The block's lattice: entries are ordered by block0 (strictly increasing,
@@ -448,60 +497,78 @@ void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_
     std::memcpy(dst, &e, sizeof e);
 }
 
-template <class T, bool COL>
+template <class T, bool COL, bool PLAQ>
 static void launch_hb_mode(const Links<T> &U, const Geom &g, int mu, int par, double beta, uint32_t k0,
                            uint32_t k1, uint32_t c1, uint32_t sweep, const uint32_t *d_sweep, uint32_t *flags,
-                           hipStream_t st)
+                           double *pp, hipStream_t st)
 {
     const dim3 grid(blocks_for(g.half)), block(kBlock);
     switch (mu) {
-    case 0: heatbath_kernel<T, 0, COL><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags); break;
-    case 1: heatbath_kernel<T, 1, COL><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags); break;
-    case 2: heatbath_kernel<T, 2, COL><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags); break;
-    default: heatbath_kernel<T, 3, COL><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags); break;
+    case 0: heatbath_kernel<T, 0, COL, false><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags, pp); break;
+    case 1: heatbath_kernel<T, 1, COL, PLAQ><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags, pp); break;
+    case 2: heatbath_kernel<T, 2, COL, PLAQ><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags, pp); break;
+    default: heatbath_kernel<T, 3, COL, PLAQ><<<grid, block, 0, st>>>(U, g, par, beta, k0, k1, c1, sweep, d_sweep, flags, pp); break;
     }
 }
 
+// plaq_partials != nullptr (class (mu >= 1, odd) of a lattice's last sweep):
+// the class also writes its planes' plaquette partials.
 template <class T>
 static void launch_hb(const LaunchArgs &a, const Geom &g, int mu, int par, double beta, uint64_t seed,
-                      uint32_t sweep, const uint32_t *d_sweep, hipStream_t st)
+                      uint32_t sweep, const uint32_t *d_sweep, double *plaq_partials, hipStream_t st)
 {
     const Links<T> U = links_of<T>(a);
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = (uint32_t)mu + 4u * 1u + 16u * (uint32_t)a.lattice_id;
-    if (col_addressing_ok(g))
-        launch_hb_mode<T, true>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, st);
+    const bool col = col_addressing_ok(g), plaq = plaq_partials != nullptr;
+    if (col && plaq)
+        launch_hb_mode<T, true, true>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, plaq_partials, st);
+    else if (col)
+        launch_hb_mode<T, true, false>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, nullptr, st);
+    else if (plaq)
+        launch_hb_mode<T, false, true>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, plaq_partials, st);
     else
-        launch_hb_mode<T, false>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, st);
+        launch_hb_mode<T, false, false>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, nullptr, st);
 }
 
-template <class T, bool COL, bool CAP>
-static void launch_or_mode(const Links<T> &U, const Geom &g, int mu, int par, uint32_t *flags, hipStream_t st)
+template <class T, bool COL, bool CAP, bool PLAQ>
+static void launch_or_mode(const Links<T> &U, const Geom &g, int mu, int par, uint32_t *flags, double *pp,
+                           hipStream_t st)
 {
     const dim3 grid(blocks_for(g.half)), block(kBlock);
     switch (mu) {
-    case 0: overrelax_kernel<T, 0, COL, CAP><<<grid, block, 0, st>>>(U, g, par, flags); break;
-    case 1: overrelax_kernel<T, 1, COL, CAP><<<grid, block, 0, st>>>(U, g, par, flags); break;
-    case 2: overrelax_kernel<T, 2, COL, CAP><<<grid, block, 0, st>>>(U, g, par, flags); break;
-    default: overrelax_kernel<T, 3, COL, CAP><<<grid, block, 0, st>>>(U, g, par, flags); break;
+    case 0: overrelax_kernel<T, 0, COL, CAP, false><<<grid, block, 0, st>>>(U, g, par, flags, pp); break;
+    case 1: overrelax_kernel<T, 1, COL, CAP, PLAQ><<<grid, block, 0, st>>>(U, g, par, flags, pp); break;
+    case 2: overrelax_kernel<T, 2, COL, CAP, PLAQ><<<grid, block, 0, st>>>(U, g, par, flags, pp); break;
+    default: overrelax_kernel<T, 3, COL, CAP, PLAQ><<<grid, block, 0, st>>>(U, g, par, flags, pp); break;
     }
 }
 
+template <class T, bool COL, bool CAP>
+static void launch_or_cap(const Links<T> &U, const Geom &g, int mu, int par, uint32_t *flags, double *pp,
+                          hipStream_t st)
+{
+    if (pp)
+        launch_or_mode<T, COL, CAP, true>(U, g, mu, par, flags, pp, st);
+    else
+        launch_or_mode<T, COL, CAP, false>(U, g, mu, par, flags, nullptr, st);
+}
+
 template <class T>
-static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, hipStream_t st)
+static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, double *plaq_partials, hipStream_t st)
 {
     const Links<T> U = links_of<T>(a);
     const bool cap = residency_cap_pays(g);
     if (col_addressing_ok(g)) {
         if (cap)
-            launch_or_mode<T, true, true>(U, g, mu, par, a.flags, st);
+            launch_or_cap<T, true, true>(U, g, mu, par, a.flags, plaq_partials, st);
         else
-            launch_or_mode<T, true, false>(U, g, mu, par, a.flags, st);
+            launch_or_cap<T, true, false>(U, g, mu, par, a.flags, plaq_partials, st);
     } else {
         if (cap)
-            launch_or_mode<T, false, true>(U, g, mu, par, a.flags, st);
+            launch_or_cap<T, false, true>(U, g, mu, par, a.flags, plaq_partials, st);
         else
-            launch_or_mode<T, false, false>(U, g, mu, par, a.flags, st);
+            launch_or_cap<T, false, false>(U, g, mu, par, a.flags, plaq_partials, st);
     }
 }
 
@@ -518,22 +585,22 @@ void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st)
 }
 
 void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, const uint32_t *d_sweep,
-                     int mu, int par, hipStream_t st)
+                     int mu, int par, double *plaq_partials, hipStream_t st)
 {
     const Geom g = make_geom(a.n, a.tile, a.tile_y);
     if (a.prec == kF32)
-        launch_hb<float>(a, g, mu, par, beta, seed, sweep, d_sweep, st);
+        launch_hb<float>(a, g, mu, par, beta, seed, sweep, d_sweep, plaq_partials, st);
     else
-        launch_hb<double>(a, g, mu, par, beta, seed, sweep, d_sweep, st);
+        launch_hb<double>(a, g, mu, par, beta, seed, sweep, d_sweep, plaq_partials, st);
 }
 
-void launch_overrelax(const LaunchArgs &a, int mu, int par, hipStream_t st)
+void launch_overrelax(const LaunchArgs &a, int mu, int par, double *plaq_partials, hipStream_t st)
 {
     const Geom g = make_geom(a.n, a.tile, a.tile_y);
     if (a.prec == kF32)
-        launch_or<float>(a, g, mu, par, st);
+        launch_or<float>(a, g, mu, par, plaq_partials, st);
     else
-        launch_or<double>(a, g, mu, par, st);
+        launch_or<double>(a, g, mu, par, plaq_partials, st);
 }
 
 template <class T>

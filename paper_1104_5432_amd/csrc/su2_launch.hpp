@@ -37,14 +37,17 @@ uint64_t batch_entry_bytes();
 void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_t nblocks, void *dst);
 
 void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st);
+// plaq_partials: null, or (classes (mu >= 1, odd) of a sweep that should
+// leave the plaquette behind) the plaquette-partials region of the workspace.
 void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, const uint32_t *d_sweep,
-                     int mu, int par, hipStream_t st);
+                     int mu, int par, double *plaq_partials, hipStream_t st);
 void launch_heatbath_batch(const void *d_table, int count, int prec, uint32_t total_blocks, int mu, int par,
                            uint64_t seed, uint32_t sweep, const uint32_t *d_sweep, hipStream_t st);
 void launch_overrelax_batch(const void *d_table, int count, int prec, uint32_t total_blocks, int mu, int par,
                             hipStream_t st);
 void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st);
-void launch_overrelax(const LaunchArgs &a, int mu, int par, hipStream_t st);
+void launch_overrelax(const LaunchArgs &a, int mu, int par, double *plaq_partials, hipStream_t st);
+void launch_plaquette_sum(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st);
 void launch_measure(const LaunchArgs &a, const WorkLayout &w, double *d_plaq, double *d_poly, double *d_corr,

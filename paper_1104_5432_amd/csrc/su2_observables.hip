@@ -16,41 +16,6 @@ static Links<T> links_of(const LaunchArgs &a)
     return L;
 }
 
-// ---------------------------------------------------------------------------
-// Reductions.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v += __shfl_down(v, off, 64);
-    return v;
-}
-
-// Sum NV values over the block; thread 0 returns the totals.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*lds)[NV])
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        v[j] = wave_sum(v[j]);
-    if (lane == 0)
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            lds[wave][j] = v[j];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            double s = 0.0;
-            for (int w = 0; w < kBlock / 64; ++w)
-                s += lds[w][j];
-            v[j] = s;
-        }
-    }
-}
-
 // Plaquettes: every site x sums (1/2) Tr of its six plaquettes
 // U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+, mu < nu, in FP64.  A thread
 // takes one cb index and both parities; blocks walk the lattice in the
@@ -272,6 +237,15 @@ __global__ void plaq_total_kernel(double *out)
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+// The plane partials a measured sweep left in the plaquette region (one per
+// block of the class grid and plane) summed into d_out[0..6].
+void launch_plaquette_sum(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
+{
+    double *partials = reinterpret_cast<double *>(a.work + w.off_plaq);
+    colsum_kernel<<<6, kBlock, 0, st>>>(partials, w.nblk_plaq, 1.0 / (double)a.volume, d_out + 1);
+    plaq_total_kernel<<<1, 64, 0, st>>>(d_out);
+}
+
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
 {
     // The lattice's strip width, but whole columns: with row ranges the

@@ -307,6 +307,39 @@ def test_single_pass_measurement_matches_oracle(su2, n, prec):
     assert _maxdiff(corr.cpu().numpy(), corr_sep.cpu().numpy()) <= tol_sep
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("n", SHAPES)
+def test_plaquette_from_last_sweep(su2, n, prec):
+    # su2_heatbath_sweep_measured / su2_overrelax_measured: the links are
+    # bitwise those of the plain sweeps; the plaquette is that of the final
+    # configuration, against the oracle on the links the GPU holds and
+    # against the separate plaquette pass
+    U0 = oracle.init_hot(n, 63)
+    a, b = _lat(su2, n, prec, U0), _lat(su2, n, prec, U0)
+    tol = 1e-13 if prec == "f64" else 2e-6
+    tol_sep = 1e-14 if prec == "f64" else 2e-6
+    for s in range(2):
+        su2.su2_heatbath_sweep(a, 2.3, 63, s)
+        m_hb = su2.su2_heatbath_sweep_measured(b, 2.3, 63, s).clone()
+        _sync()
+        assert torch.equal(a.links, b.links)
+        Uc = su2.to_canonical(b).numpy()
+        su2.su2_overrelax(a, 2)
+        m_or = su2.su2_overrelax_measured(b, 2).clone()
+        _sync()
+        assert torch.equal(a.links, b.links)
+        sep = su2.su2_plaquette(b)
+        m_zero = su2.su2_overrelax_measured(b, 0)   # no sweep: the plain pass
+        _sync()
+        assert torch.equal(m_zero, sep)
+        assert _maxdiff(m_or.cpu().numpy(), sep.cpu().numpy()) <= tol_sep
+        for m, U in ((m_hb, Uc), (m_or, su2.to_canonical(b).numpy())):
+            p, planes = oracle.plaquette(n, U)
+            g = m.cpu().numpy()
+            assert abs(g[0] - p) <= tol and np.max(np.abs(g[1:] - planes)) <= tol
+    assert _flags(su2, b) == 0
+
+
 def test_observables_gauge_invariant_on_gpu(su2):
     n = (8, 6, 4, 6)
     U0 = oracle.init_hot(n, 17)
@@ -360,6 +393,12 @@ def test_full_size_64(su2, prec):
     assert abs(g[0] - p) <= tol and np.max(np.abs(g[1:] - planes)) <= tol
     g = poly.cpu().numpy()
     assert abs(g[0] - lm) <= tol and abs(g[1] - la) <= tol
+    # the plaquette measured by the last overrelaxation sweep (as the
+    # benchmark step takes it) against the separate pass on its result
+    m = su2.su2_overrelax_measured(lat, 1)
+    sep = su2.su2_plaquette(lat)
+    _sync()
+    assert _maxdiff(m.cpu().numpy(), sep.cpu().numpy()) <= (1e-14 if prec == "f64" else 1e-6)
     assert _flags(su2, lat) == 0
 
 
@@ -372,6 +411,7 @@ def test_block_order_does_not_change_results(su2, prec):
     # bit-identical links; plaquette sums differ only in summation order
     # (walks with row ranges of 256/S cb indices: S <= 4 column-addressed,
     # S = 8, 16 coordinate-addressed)
+    # (the plaquette measured by a last sweep sums per block of the walk)
     n = (32, 16, 8, 4)
     links, plaqs = [], []
     for w, sy in ((-1, 0), (0, 0), (1, 0), (2, 0), (4, 0), (8, 0), (1, 2), (8, 4), (2, 8), (4, 16)):
@@ -379,12 +419,16 @@ def test_block_order_does_not_change_results(su2, prec):
         su2.su2_init_hot(lat, 5)
         su2.su2_heatbath_sweep(lat, 2.3, 5, 0)
         su2.su2_overrelax(lat, 2)
-        plaqs.append(su2.su2_plaquette(lat).clone())
+        got = [su2.su2_plaquette(lat).clone()]
+        got.append(su2.su2_heatbath_sweep_measured(lat, 2.3, 5, 1).clone())
+        got.append(su2.su2_overrelax_measured(lat, 1).clone())
+        plaqs.append(got)
         _sync()
         links.append(lat.links.clone())
     for k in range(1, len(links)):
         assert torch.equal(links[0], links[k])
-        assert torch.max(torch.abs(plaqs[0] - plaqs[k])).item() <= 1e-15
+        for x, y in zip(plaqs[0], plaqs[k]):
+            assert torch.max(torch.abs(x - y)).item() <= 1e-15
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
