@@ -714,12 +714,36 @@ __device__ __forceinline__ void reserve_lds_for_residency()
 // Deterministic reductions: wave64 shuffles, then an LDS tree over the
 // block's waves in a fixed order.
 // ---------------------------------------------------------------------------
+// A DPP lane move of a double within rows of 16 lanes (two 32-bit moves;
+// every source lane of the controls used below is valid).
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_double(double v, int lane)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), returned in every
+// lane, in a fixed order: pairs, quads, half rows and rows by DPP moves
+// (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror),
+// then the four row sums read out as scalars.  No LDS traffic.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        v += __shfl_down(v, off, 64);
-    return v;
+    v += dpp_double<0xB1>(v);
+    v += dpp_double<0x4E>(v);
+    v += dpp_double<0x141>(v);
+    v += dpp_double<0x140>(v);
+    return (readlane_double(v, 0) + readlane_double(v, 16)) + (readlane_double(v, 32) + readlane_double(v, 48));
 }
 
 // Sum NV values over the block; thread 0 returns the totals.
