@@ -139,7 +139,7 @@ def scan(args):
     32^3x4, 48^3x6, 64^3x8, beta_j = 2.2 + 0.5 j/15, lattice_id j, one
     captured graph per sweep (batched heat bath reading the sweep index from
     device memory, args.or_per_hb batched overrelaxation sweeps, Polyakov
-    loop and correlator of every lattice, sweep advance)."""
+    loop and correlator of all lattices in three launches, sweep advance)."""
     import torch
     import paper_1104_5432_amd as su2
 
@@ -152,24 +152,22 @@ def scan(args):
         betas.append(2.2 + 0.5 * j / 15)
     batch = su2.Batch(lats, betas)
     d_sweep = torch.zeros(1, dtype=torch.int32, device="cuda:0")
-    poly = [torch.zeros(2, dtype=torch.float64, device="cuda:0") for _ in lats]
-    corr = [torch.zeros(lat.n[0] // 2, dtype=torch.float64, device="cuda:0") for lat in lats]
+    poly = torch.zeros((16, 2), dtype=torch.float64, device="cuda:0")
+    corr = torch.zeros((16, max(min(lat.n[:3]) // 2 for lat in lats)), dtype=torch.float64, device="cuda:0")
     hist = torch.zeros((args.steps + args.warmup, 16, 2), dtype=torch.float64, device="cuda:0")
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         su2.su2_batch_heatbath_sweep(batch, args.seed, d_sweep=d_sweep)
         su2.su2_batch_overrelax(batch, args.or_per_hb)
-        for lat, q, c in zip(lats, poly, corr):
-            su2.su2_polyakov(lat, q, c)
+        su2.su2_batch_polyakov(batch, poly, corr)
         su2.su2_sweep_advance(d_sweep)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
     def sweep(k):
         graph.replay()
-        for j in range(16):
-            hist[k, j].copy_(poly[j], non_blocking=True)
+        hist[k].copy_(poly, non_blocking=True)
 
     for k in range(args.warmup):
         sweep(k)

@@ -202,6 +202,19 @@ int su2_batch_heatbath_sweep(const su2_lattice_t *lats, int32_t count, const voi
 int su2_batch_overrelax(const su2_lattice_t *lats, int32_t count, const void *d_table, int32_t n_sweeps,
                         void *stream);
 
+/* Polyakov loop and on-axis correlator (Sec. 2.2, eqs. (1) and (3)) of every
+ * lattice of the batch, each exactly as su2_polyakov computes it (the same
+ * block partials and summation order, so bitwise the same values), in three
+ * launches for the whole batch.  d_poly: device, 2*count doubles, [2j] the
+ * mean L and [2j+1] the mean |L| of lattice j.  d_corr: device,
+ * count*corr_stride doubles, or NULL for no correlator; row j holds C(r),
+ * r = 1..min(Nx,Ny,Nz)/2 of lattice j, and its entries beyond are left
+ * untouched; corr_stride must be >= the largest min(Nx,Ny,Nz)/2 of the
+ * batch.  Uses each lattice's workspace; lats and d_table as for the other
+ * batched calls (the table of su2_batch_fill for these descriptors). */
+int su2_batch_polyakov(const su2_lattice_t *lats, int32_t count, const void *d_table, double *d_poly,
+                       double *d_corr, int32_t corr_stride, void *stream);
+
 /* *d_sweep += 1 on the device (d_sweep: device, one uint32). */
 int su2_sweep_advance(uint32_t *d_sweep, void *stream);
 

@@ -71,6 +71,7 @@ _SIGNATURES = {
     "su2_batch_heatbath_sweep": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, ctypes.c_uint64, ctypes.c_uint32, _VP,
                                                 _VP]),
     "su2_batch_overrelax": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, ctypes.c_int32, _VP]),
+    "su2_batch_polyakov": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_int32, _VP]),
     "su2_sweep_advance": (ctypes.c_int, [_VP, _VP]),
     "su2_lp_param_count": (ctypes.c_int32, []),
     "su2_lp_workspace_bytes": (ctypes.c_uint64, [_I4]),
@@ -288,6 +289,28 @@ def su2_batch_heatbath_sweep(batch, seed, sweep=0, d_sweep=None, stream=None):
 def su2_batch_overrelax(batch, n_sweeps=1, stream=None):
     _check(lib.su2_batch_overrelax(batch.descs, batch.count, batch.table.data_ptr(), int(n_sweeps),
                                    _stream(stream)))
+
+
+def su2_batch_polyakov(batch, poly=None, corr=None, with_corr=True, stream=None):
+    """Polyakov loop (and correlator) of every lattice of the batch, bitwise
+    as su2_polyakov of each.  Returns (poly [count, 2] float64, corr
+    [count, stride] float64 or None); row j of corr holds C(r), r = 1..
+    min(Nx,Ny,Nz)/2 of lattice j, and is left untouched beyond."""
+    dev = batch.lattices[0].device
+    stride = max(min(lat.n[:3]) // 2 for lat in batch.lattices)
+    if poly is None:
+        poly = torch.empty((batch.count, 2), dtype=torch.float64, device=dev)
+    if with_corr and corr is None:
+        corr = torch.zeros((batch.count, stride), dtype=torch.float64, device=dev)
+    if poly.shape != (batch.count, 2) or poly.dtype != torch.float64 or not poly.is_contiguous():
+        raise ValueError("poly must be a contiguous float64 tensor of shape (count, 2)")
+    if corr is not None:
+        if corr.dim() != 2 or corr.shape[0] != batch.count or corr.dtype != torch.float64 or corr.stride(1) != 1:
+            raise ValueError("corr must be a float64 tensor of shape (count, stride) with unit column stride")
+        stride = corr.stride(0)
+    _check(lib.su2_batch_polyakov(batch.descs, batch.count, batch.table.data_ptr(), poly.data_ptr(),
+                                  corr.data_ptr() if corr is not None else None, int(stride), _stream(stream)))
+    return poly, corr
 
 
 def su2_sweep_advance(d_sweep, stream=None):

@@ -401,15 +401,47 @@ int su2_batch_fill(const su2_lattice_t *lats, const double *betas, int32_t count
     for (int j = 0; j < count; ++j)
         if ((rc = check_beta(betas[j])))
             return rc;
-    uint32_t block0 = 0;
+    su2::BatchOffsets o = {};
     for (int j = 0; j < count; ++j) {
         su2::LaunchArgs a;
-        check_lattice(&lats[j], &a, nullptr);
-        const uint32_t nb = round8(su2::class_blocks(a));
-        su2::fill_batch_entry(a, betas[j], block0, nb, static_cast<char *>(host_table) + j * su2::batch_entry_bytes());
-        block0 += nb;
+        su2::WorkLayout w;
+        check_lattice(&lats[j], &a, &w);
+        o.nblocks = round8(su2::class_blocks(a));
+        su2::fill_batch_entry(a, w, betas[j], o, static_cast<char *>(host_table) + j * su2::batch_entry_bytes());
+        o.block0 += o.nblocks;
+        o.pblock0 += w.nblk_poly;
+        o.cblock0 += w.nblk_corr * (uint32_t)w.rmax;
+        o.ocol0 += 2u + (uint32_t)w.rmax;
     }
     return SU2_OK;
+}
+
+int su2_batch_polyakov(const su2_lattice_t *lats, int32_t count, const void *d_table, double *d_poly,
+                       double *d_corr, int32_t corr_stride, void *stream)
+{
+    int rc = check_batch(lats, count, nullptr);
+    if (rc)
+        return rc;
+    if (!d_table || !aligned(d_table, 8))
+        return fail(SU2_EINVAL, "d_table must be an 8-byte aligned device pointer");
+    if (!d_poly)
+        return fail(SU2_EINVAL, "d_poly must be a device pointer to 2*count doubles");
+    if (!aligned(d_poly, 8) || (d_corr && !aligned(d_corr, 8)))
+        return fail(SU2_EALIGN, "d_poly and d_corr must be 8-byte aligned");
+    su2::BatchPolyGrid grid = {};
+    int rmax = 0;
+    for (int j = 0; j < count; ++j) {
+        const su2::WorkLayout w = su2::work_layout(lats[j].n);
+        grid.poly_blocks += w.nblk_poly;
+        grid.corr_blocks += w.nblk_corr * (uint32_t)w.rmax;
+        grid.columns += 2u + (uint32_t)w.rmax;
+        rmax = w.rmax > rmax ? w.rmax : rmax;
+    }
+    if (d_corr && corr_stride < rmax)
+        return fail(SU2_EINVAL, "corr_stride must be >= min(Nx,Ny,Nz)/2 of every lattice of the batch");
+    su2::launch_polyakov_batch(d_table, count, lats[0].prec, grid, d_poly, d_corr, (uint32_t)corr_stride,
+                               (hipStream_t)stream);
+    return launched();
 }
 
 int su2_batch_heatbath_sweep(const su2_lattice_t *lats, int32_t count, const void *d_table, uint64_t seed,

@@ -213,7 +213,32 @@ struct BatchEntry {
     uint32_t block0;  // first block of this lattice in the batched grid (multiple of 8)
     uint32_t nblocks; // blocks of this lattice (multiple of 8)
     uint32_t col;     // 1: the lattice qualifies for column addressing
+    // Polyakov loop and correlator (the regions of the lattice's workspace
+    // and the block counts its single-lattice launches use)
+    double *lfield;    // L of every spatial site
+    double *poly_part; // 2 columns of pnblk block partials
+    double *corr_part; // rmax columns of cnblk block partials
+    uint32_t pblock0, pnblk; // Polyakov blocks: first in the batched grid, count
+    uint32_t cblock0, cnblk; // correlator blocks: first in the batched grid, count per separation
+    uint32_t rmax, ocol0;    // separations; first of the lattice's 2 + rmax output columns
 };
+
+// Index of the batch entry whose range of the batched grid holds block b:
+// the last entry with (entry.*FIRST) <= b (the firsts ascend).  Each lane
+// tests one entry and a wave ballot counts the hits, so the lookup is one
+// round of independent loads per 64 lattices.
+template <uint32_t BatchEntry::*FIRST>
+__device__ __forceinline__ int find_entry_index(const BatchEntry *tab, int count, uint32_t b)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    int hits = 0;
+    for (int base = 0; base < count; base += 64) {
+        const int j = base + lane;
+        const bool le = j < count && tab[j].*FIRST <= b;
+        hits += (int)__popcll(__ballot(le));
+    }
+    return __builtin_amdgcn_readfirstlane(hits > 0 ? hits - 1 : 0);
+}
 
 // ---------------------------------------------------------------------------
 // Geometry construction (host).  Walk of a class: tile > 0 is the strip width

@@ -360,19 +360,12 @@ __global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, i
 
 // The block's lattice: entries are ordered by block0 (strictly increasing,
 // entry 0 at block 0), so it is the last entry with block0 <= blockIdx.x.
-// Each lane tests one entry and a wave ballot counts the hits: one round of
-// independent loads for up to 64 lattices instead of a chain of dependent
-// ones (which, exposed at low residency, cost more than the update).
+// One round of independent loads for up to 64 lattices instead of a chain
+// of dependent ones (which, exposed at low residency, cost more than the
+// update).
 __device__ __forceinline__ const BatchEntry &find_entry(const BatchEntry *tab, int count)
 {
-    const int lane = (int)(threadIdx.x & 63u);
-    int hits = 0;
-    for (int base = 0; base < count; base += 64) {
-        const int j = base + lane;
-        const bool le = j < count && tab[j].block0 <= blockIdx.x;
-        hits += (int)__popcll(__ballot(le));
-    }
-    return tab[__builtin_amdgcn_readfirstlane(hits > 0 ? hits - 1 : 0)];
+    return tab[find_entry_index<&BatchEntry::block0>(tab, count, blockIdx.x)];
 }
 
 template <class T, int MU>
@@ -483,7 +476,7 @@ uint64_t batch_entry_bytes()
     return sizeof(BatchEntry);
 }
 
-void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_t nblocks, void *dst)
+void fill_batch_entry(const LaunchArgs &a, const WorkLayout &w, double beta, const BatchOffsets &o, void *dst)
 {
     BatchEntry e = {};
     e.g = make_geom(a.n, a.tile, a.tile_y);
@@ -492,8 +485,17 @@ void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_
     e.beta = beta;
     e.lid16 = 16u * (uint32_t)a.lattice_id;
     e.col = col_addressing_ok(e.g) ? 1u : 0u;
-    e.block0 = block0;
-    e.nblocks = nblocks;
+    e.block0 = o.block0;
+    e.nblocks = o.nblocks;
+    e.lfield = reinterpret_cast<double *>(a.work + w.off_lfield);
+    e.poly_part = reinterpret_cast<double *>(a.work + w.off_poly);
+    e.corr_part = reinterpret_cast<double *>(a.work + w.off_corr);
+    e.pblock0 = o.pblock0;
+    e.pnblk = w.nblk_poly;
+    e.cblock0 = o.cblock0;
+    e.cnblk = w.nblk_corr;
+    e.rmax = (uint32_t)w.rmax;
+    e.ocol0 = o.ocol0;
     std::memcpy(dst, &e, sizeof e);
 }
 

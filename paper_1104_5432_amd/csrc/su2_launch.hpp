@@ -34,7 +34,17 @@ WorkLayout work_layout(const int32_t n[4]);
 
 uint32_t class_blocks(const LaunchArgs &a);
 uint64_t batch_entry_bytes();
-void fill_batch_entry(const LaunchArgs &a, double beta, uint32_t block0, uint32_t nblocks, void *dst);
+// A lattice's ranges in the batched grids: update blocks (block0, nblocks),
+// Polyakov blocks (pblock0), correlator blocks (cblock0) and output columns
+// of the batched Polyakov sums (ocol0); each the sum over earlier lattices.
+struct BatchOffsets {
+    uint32_t block0, nblocks, pblock0, cblock0, ocol0;
+};
+void fill_batch_entry(const LaunchArgs &a, const WorkLayout &w, double beta, const BatchOffsets &o, void *dst);
+// Grid sizes of the batched Polyakov launches, from the same descriptors.
+struct BatchPolyGrid {
+    uint32_t poly_blocks, corr_blocks, columns; // columns with the correlator (2 + rmax per lattice)
+};
 
 void launch_init(const LaunchArgs &a, int hot, uint64_t seed, hipStream_t st);
 // plaq_partials: null, or (classes (mu >= 1, odd) of a sweep that should
@@ -50,6 +60,9 @@ void launch_overrelax(const LaunchArgs &a, int mu, int par, double *plaq_partial
 void launch_plaquette_sum(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st);
+// d_corr null: no correlator.
+void launch_polyakov_batch(const void *d_table, int count, int prec, const BatchPolyGrid &grid, double *d_poly,
+                           double *d_corr, uint32_t corr_stride, hipStream_t st);
 void launch_measure(const LaunchArgs &a, const WorkLayout &w, double *d_plaq, double *d_poly, double *d_corr,
                     hipStream_t st);
 void launch_get_flags(const LaunchArgs &a, uint32_t *d_flags, hipStream_t st);

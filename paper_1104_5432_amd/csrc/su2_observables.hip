@@ -1,7 +1,8 @@
 // su2_observables.hip -- gfx950 kernels of the measured observables: the
 // mean plaquette (per plane), the Polyakov loop and its on-axis correlator.
-// All sums are FP64 and deterministic: wave64 shuffles, an LDS tree, one
-// partial per block (stored column by column) and a fixed-order final pass.
+// All sums are FP64 and deterministic: fixed-order wave64 sums, an LDS
+// tree, one partial per block (stored column by column) and a fixed-order
+// final pass.
 #include "su2_device.hpp"
 #include "su2_launch.hpp"
 
@@ -144,13 +145,16 @@ __global__ __launch_bounds__(kBlock) void measure_kernel(Links<T> U, Geom g, dou
             partials[(size_t)j * gridDim.x + blockIdx.x] = acc[j];
 }
 
-// Polyakov loop at each spatial site: ordered product of the Nt temporal links.
+// Polyakov loop at each spatial site: ordered product of the Nt temporal
+// links.  Block b of nb (grid-stride over the spatial sites) writes its
+// partial sums of L and |L| to partials[b] and partials[nb + b].
 template <class T>
-__global__ __launch_bounds__(kBlock) void polyakov_kernel(Links<T> U, Geom g, double *Lfield, double *partials)
+__device__ __forceinline__ void polyakov_body(const Links<T> &U, const Geom &g, double *Lfield, double *partials,
+                                              uint32_t b, uint32_t nb)
 {
     __shared__ double lds[kBlock / 64][2];
     double acc[2] = {0, 0};
-    for (uint32_t sp = blockIdx.x * kBlock + threadIdx.x; sp < g.vs; sp += gridDim.x * kBlock) {
+    for (uint32_t sp = b * kBlock + threadIdx.x; sp < g.vs; sp += nb * kBlock) {
         const uint32_t yz = fdiv(sp, g.div_nx);
         const uint32_t x = sp - yz * (uint32_t)g.n[0];
         const uint32_t z = fdiv(yz, g.div_ny);
@@ -168,21 +172,27 @@ __global__ __launch_bounds__(kBlock) void polyakov_kernel(Links<T> U, Geom g, do
     }
     block_sum<2>(acc, lds);
     if (threadIdx.x == 0) {
-        partials[blockIdx.x] = acc[0];
-        partials[(size_t)gridDim.x + blockIdx.x] = acc[1];
+        partials[b] = acc[0];
+        partials[(size_t)nb + b] = acc[1];
     }
 }
 
-// On-axis Polyakov correlator: for r = 1..R (blockIdx.y = r - 1),
-// sum_x L(x)(L(x+r e_x) + L(x+r e_y) + L(x+r e_z)); one partial per block,
-// stored column r-1.
-__global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, Geom g, double *partials)
+template <class T>
+__global__ __launch_bounds__(kBlock) void polyakov_kernel(Links<T> U, Geom g, double *Lfield, double *partials)
+{
+    polyakov_body<T>(U, g, Lfield, partials, blockIdx.x, gridDim.x);
+}
+
+// On-axis Polyakov correlator at separation r:
+// sum_x L(x)(L(x+r e_x) + L(x+r e_y) + L(x+r e_z)); block b of nb writes
+// its partial to partials[(r-1) nb + b] (column r-1).
+__device__ __forceinline__ void polycorr_body(const double *Lfield, const Geom &g, double *partials, uint32_t r,
+                                              uint32_t b, uint32_t nb)
 {
     __shared__ double lds[kBlock / 64][1];
     const uint32_t nx = (uint32_t)g.n[0], ny = (uint32_t)g.n[1], nz = (uint32_t)g.n[2];
-    const uint32_t r = blockIdx.y + 1u;
     double acc[1] = {0.0};
-    for (uint32_t sp = blockIdx.x * kBlock + threadIdx.x; sp < g.vs; sp += gridDim.x * kBlock) {
+    for (uint32_t sp = b * kBlock + threadIdx.x; sp < g.vs; sp += nb * kBlock) {
         const uint32_t yz = fdiv(sp, g.div_nx);
         const uint32_t x = sp - yz * nx;
         const uint32_t z = fdiv(yz, g.div_ny);
@@ -197,16 +207,19 @@ __global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, 
     }
     block_sum<1>(acc, lds);
     if (threadIdx.x == 0)
-        partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = acc[0];
+        partials[(size_t)(r - 1u) * nb + b] = acc[0];
 }
 
-// out[c] = scale * sum_b partials[c*nblk + b] (partials stored column by
-// column, so the reads are contiguous), one block per column, fixed order.
-__global__ __launch_bounds__(kBlock) void colsum_kernel(const double *partials, uint32_t nblk, double scale,
-                                                         double *out)
+// Separation r = blockIdx.y + 1.
+__global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, Geom g, double *partials)
+{
+    polycorr_body(Lfield, g, partials, blockIdx.y + 1u, blockIdx.x, gridDim.x);
+}
+
+// *out = scale * sum_b col[b], b < nblk, in a fixed order (one block).
+__device__ __forceinline__ void colsum_body(const double *col, uint32_t nblk, double scale, double *out)
 {
     __shared__ double lds[kBlock / 64][1];
-    const double *col = partials + (size_t)blockIdx.x * nblk;
     double acc[1] = {0.0};
     // Eight loads are issued before their (in-order) sums; one load per
     // iteration made the loop a chain of dependent global-memory latencies.
@@ -224,7 +237,63 @@ __global__ __launch_bounds__(kBlock) void colsum_kernel(const double *partials, 
         acc[0] += col[b];
     block_sum<1>(acc, lds);
     if (threadIdx.x == 0)
-        out[blockIdx.x] = acc[0] * scale;
+        *out = acc[0] * scale;
+}
+
+// out[c] = scale * sum_b partials[c*nblk + b] (partials stored column by
+// column, so the reads are contiguous), one block per column c.
+__global__ __launch_bounds__(kBlock) void colsum_kernel(const double *partials, uint32_t nblk, double scale,
+                                                         double *out)
+{
+    colsum_body(partials + (size_t)blockIdx.x * nblk, nblk, scale, out + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Polyakov loop and correlator of every lattice of a batch, three launches
+// in all.  Each lattice keeps the block counts, partial layout and summation
+// order of its single-lattice launches, so its results are bitwise those of
+// su2_polyakov; a block finds its lattice from the table's ranges.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(kBlock) void polyakov_batch_kernel(const BatchEntry *tab, int count)
+{
+    const BatchEntry &e = tab[find_entry_index<&BatchEntry::pblock0>(tab, count, blockIdx.x)];
+    Links<T> U;
+    U.p = reinterpret_cast<decltype(U.p)>(e.links);
+    U.half = e.g.half;
+    polyakov_body<T>(U, e.g, e.lfield, e.poly_part, blockIdx.x - e.pblock0, e.pnblk);
+}
+
+// A lattice's rmax * cnblk blocks: separation r = local / cnblk + 1.
+__global__ __launch_bounds__(kBlock) void polycorr_batch_kernel(const BatchEntry *tab, int count)
+{
+    const BatchEntry &e = tab[find_entry_index<&BatchEntry::cblock0>(tab, count, blockIdx.x)];
+    const uint32_t local = blockIdx.x - e.cblock0;
+    const uint32_t rm1 = local / e.cnblk;
+    polycorr_body(e.lfield, e.g, e.corr_part, rm1 + 1u, local - rm1 * e.cnblk, e.cnblk);
+}
+
+// One block per output: lattice j's columns 0, 1 (mean L, mean |L|) go to
+// d_poly[2j], d_poly[2j+1]; with the correlator, its columns 2 + (r-1) go to
+// d_corr[j * corr_stride + r - 1].
+__global__ __launch_bounds__(kBlock) void polysum_batch_kernel(const BatchEntry *tab, int count, double *d_poly,
+                                                                double *d_corr, uint32_t corr_stride)
+{
+    int j;
+    uint32_t c;
+    if (d_corr) {
+        j = find_entry_index<&BatchEntry::ocol0>(tab, count, blockIdx.x);
+        c = blockIdx.x - tab[j].ocol0;
+    } else {
+        j = (int)(blockIdx.x >> 1);
+        c = blockIdx.x & 1u;
+    }
+    const BatchEntry &e = tab[j];
+    if (c < 2u)
+        colsum_body(e.poly_part + (size_t)c * e.pnblk, e.pnblk, 1.0 / (double)e.g.vs, d_poly + 2 * j + c);
+    else
+        colsum_body(e.corr_part + (size_t)(c - 2u) * e.cnblk, e.cnblk, 1.0 / (3.0 * (double)e.g.vs),
+                    d_corr + (size_t)j * corr_stride + (c - 2u));
 }
 
 // d_out[0] = mean of the six plane averages d_out[1..6].
@@ -283,6 +352,20 @@ void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, do
         polycorr_kernel<<<dim3(w.nblk_corr, (uint32_t)w.rmax), kBlock, 0, st>>>(Lf, g, cp);
         colsum_kernel<<<w.rmax, kBlock, 0, st>>>(cp, w.nblk_corr, 1.0 / (3.0 * (double)g.vs), d_corr);
     }
+}
+
+void launch_polyakov_batch(const void *d_table, int count, int prec, const BatchPolyGrid &grid, double *d_poly,
+                           double *d_corr, uint32_t corr_stride, hipStream_t st)
+{
+    const BatchEntry *tab = static_cast<const BatchEntry *>(d_table);
+    if (prec == kF32)
+        polyakov_batch_kernel<float><<<grid.poly_blocks, kBlock, 0, st>>>(tab, count);
+    else
+        polyakov_batch_kernel<double><<<grid.poly_blocks, kBlock, 0, st>>>(tab, count);
+    if (d_corr)
+        polycorr_batch_kernel<<<grid.corr_blocks, kBlock, 0, st>>>(tab, count);
+    const uint32_t outs = d_corr ? grid.columns : 2u * (uint32_t)count;
+    polysum_batch_kernel<<<outs, kBlock, 0, st>>>(tab, count, d_poly, d_corr, corr_stride);
 }
 
 void launch_measure(const LaunchArgs &a, const WorkLayout &w, double *d_plaq, double *d_poly, double *d_corr,

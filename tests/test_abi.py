@@ -125,6 +125,13 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     assert L.su2_batch_heatbath_sweep(arr, 2, 0x40004, 1, 0, None, s) == su2.SU2_EINVAL
     assert L.su2_batch_heatbath_sweep(arr, 2, 0x40000, 1, 0, 0x50002, s) == su2.SU2_EALIGN
     assert L.su2_batch_overrelax(arr, 2, 0x40000, -1, s) == su2.SU2_EINVAL
+    rmax = 4                                       # the larger min(Nx,Ny,Nz)/2 of 8^4 and 4^3x6
+    assert L.su2_batch_polyakov(arr, 2, None, 0x60000, None, 0, s) == su2.SU2_EINVAL
+    assert L.su2_batch_polyakov(arr, 2, 0x40000, None, None, 0, s) == su2.SU2_EINVAL
+    assert L.su2_batch_polyakov(arr, 2, 0x40000, 0x60001, None, 0, s) == su2.SU2_EALIGN
+    assert L.su2_batch_polyakov(arr, 2, 0x40000, 0x60000, 0x70004, rmax, s) == su2.SU2_EALIGN
+    assert L.su2_batch_polyakov(arr, 2, 0x40000, 0x60000, 0x70000, rmax - 1, s) == su2.SU2_EINVAL
+    assert L.su2_batch_polyakov(arr, 0, 0x40000, 0x60000, None, 0, s) == su2.SU2_EINVAL
     assert L.su2_sweep_advance(None, s) == su2.SU2_EINVAL
     assert L.su2_sweep_advance(0x50001, s) == su2.SU2_EALIGN
     # messages

@@ -6,6 +6,8 @@ captured-graph replay, through the C ABI.
   keyed by (seed, sweep, site, mu, kind, lattice_id) and the update of a link
   does not depend on which block or launch performs it.
 - Batch members match the FP64 oracle per link (same bound as single runs).
+- The batched Polyakov loop and correlator are bitwise the per-lattice
+  ones and leave the correlator rows beyond each lattice's range untouched.
 - A hipGraph capturing one sweep (batched heat bath with the sweep index read
   from device memory, batched overrelaxation, observables, sweep advance)
   replays bit-identically to the same calls made eagerly, replay after
@@ -65,6 +67,43 @@ def test_batch_matches_single_lattices(su2, prec):
         assert int(f.item()) == 0
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_polyakov_matches_single_lattices(su2, prec):
+    # su2_batch_polyakov: three launches for all lattices, bitwise the
+    # per-lattice su2_polyakov (same partials, same summation order)
+    seed = 91
+    lats = _fresh(su2, prec, seed)
+    batch = su2.Batch(lats, BETAS)
+    for s in range(2):
+        su2.su2_batch_heatbath_sweep(batch, seed, sweep=s)
+        su2.su2_batch_overrelax(batch, 1)
+    stride = 11                                    # wider than any min(Nx,Ny,Nz)/2 here
+    sentinel = -7.25
+    corr = torch.full((len(lats), stride), sentinel, dtype=torch.float64, device="cuda")
+    poly, corr = su2.su2_batch_polyakov(batch, corr=corr)
+    poly_nc, none = su2.su2_batch_polyakov(batch, with_corr=False)
+    _sync()
+    assert none is None
+    assert torch.equal(poly, poly_nc)
+    for j, lat in enumerate(lats):
+        q, c = su2.su2_polyakov(lat)
+        _sync()
+        r = min(lat.n[:3]) // 2
+        assert torch.equal(poly[j], q), lat.n
+        assert torch.equal(corr[j, :r], c[:r]), lat.n
+        assert torch.all(corr[j, r:] == sentinel), lat.n      # left untouched beyond rmax
+    # against the oracle on the links the GPU holds
+    for j in (0, 3):
+        Uc = su2.to_canonical(lats[j]).numpy()
+        n = lats[j].n
+        l_mean, l_abs = oracle.polyakov(n, Uc)
+        C = oracle.polyakov_corr(n, Uc)
+        tol = 1e-13 if prec == "f64" else 2e-6
+        g = poly[j].cpu().numpy()
+        assert abs(g[0] - l_mean) <= tol and abs(g[1] - l_abs) <= tol
+        assert np.max(np.abs(corr[j, :len(C)].cpu().numpy() - C)) <= tol
+
+
 def test_batch_members_match_oracle(su2):
     seed = 1234
     shapes = [(8, 8, 8, 8), (6, 4, 10, 8)]
@@ -98,6 +137,10 @@ def test_graph_replay_matches_eager(su2, prec):
     corr = [torch.zeros(max(1, min(l.n[:3]) // 2), dtype=torch.float64, device="cuda") for l in g_lats]
     _sync()
 
+    bpoly = torch.zeros((len(g_lats), 2), dtype=torch.float64, device="cuda")
+    bcorr = torch.zeros((len(g_lats), max(c.numel() for c in corr)), dtype=torch.float64, device="cuda")
+    _sync()
+
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         su2.su2_batch_heatbath_sweep(g_batch, seed, d_sweep=d_sweep)
@@ -105,6 +148,7 @@ def test_graph_replay_matches_eager(su2, prec):
         for lat, p, q, c in zip(g_lats, plaq, poly, corr):
             su2.su2_plaquette(lat, p)
             su2.su2_polyakov(lat, q, c)
+        su2.su2_batch_polyakov(g_batch, bpoly, bcorr)
         su2.su2_sweep_advance(d_sweep)
     _sync()
     # capturing must not have executed anything
@@ -123,3 +167,5 @@ def test_graph_replay_matches_eager(su2, prec):
             qe, ce = su2.su2_polyakov(lat_e)
             _sync()
             assert torch.equal(p, pe) and torch.equal(q, qe) and torch.equal(c[:len(ce)], ce), (s, lat_g.n)
+        for j, (q, c) in enumerate(zip(poly, corr)):
+            assert torch.equal(bpoly[j], q) and torch.equal(bcorr[j, :c.numel()], c), (s, j)
