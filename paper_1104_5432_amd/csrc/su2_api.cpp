@@ -410,7 +410,7 @@ int su2_batch_fill(const su2_lattice_t *lats, const double *betas, int32_t count
         su2::fill_batch_entry(a, w, betas[j], o, static_cast<char *>(host_table) + j * su2::batch_entry_bytes());
         o.block0 += o.nblocks;
         o.pblock0 += w.nblk_poly;
-        o.cblock0 += w.nblk_corr * (uint32_t)w.rmax;
+        o.cblock0 += w.nblk_corr * su2::corr_groups(w.rmax);
         o.ocol0 += 2u + (uint32_t)w.rmax;
     }
     return SU2_OK;
@@ -433,7 +433,7 @@ int su2_batch_polyakov(const su2_lattice_t *lats, int32_t count, const void *d_t
     for (int j = 0; j < count; ++j) {
         const su2::WorkLayout w = su2::work_layout(lats[j].n);
         grid.poly_blocks += w.nblk_poly;
-        grid.corr_blocks += w.nblk_corr * (uint32_t)w.rmax;
+        grid.corr_blocks += w.nblk_corr * su2::corr_groups(w.rmax);
         grid.columns += 2u + (uint32_t)w.rmax;
         rmax = w.rmax > rmax ? w.rmax : rmax;
     }

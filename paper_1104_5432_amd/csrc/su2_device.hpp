@@ -219,7 +219,7 @@ struct BatchEntry {
     double *poly_part; // 2 columns of pnblk block partials
     double *corr_part; // rmax columns of cnblk block partials
     uint32_t pblock0, pnblk; // Polyakov blocks: first in the batched grid, count
-    uint32_t cblock0, cnblk; // correlator blocks: first in the batched grid, count per separation
+    uint32_t cblock0, cnblk; // correlator blocks: first in the batched grid, count per separation group
     uint32_t rmax, ocol0;    // separations; first of the lattice's 2 + rmax output columns
 };
 

@@ -32,6 +32,14 @@ struct LaunchArgs {
 
 WorkLayout work_layout(const int32_t n[4]);
 
+// Separations of the Polyakov correlator taken by one block (one load of a
+// site's L for the group); corr_groups(rmax) groups cover r = 1..rmax.
+constexpr uint32_t kCorrGroup = 8;
+__host__ __device__ inline uint32_t corr_groups(int rmax)
+{
+    return rmax > 0 ? ((uint32_t)rmax + kCorrGroup - 1u) / kCorrGroup : 0u;
+}
+
 uint32_t class_blocks(const LaunchArgs &a);
 uint64_t batch_entry_bytes();
 // A lattice's ranges in the batched grids: update blocks (block0, nblocks),

@@ -183,37 +183,50 @@ __global__ __launch_bounds__(kBlock) void polyakov_kernel(Links<T> U, Geom g, do
     polyakov_body<T>(U, g, Lfield, partials, blockIdx.x, gridDim.x);
 }
 
-// On-axis Polyakov correlator at separation r:
-// sum_x L(x)(L(x+r e_x) + L(x+r e_y) + L(x+r e_z)); block b of nb writes
-// its partial to partials[(r-1) nb + b] (column r-1).
-__device__ __forceinline__ void polycorr_body(const double *Lfield, const Geom &g, double *partials, uint32_t r,
-                                              uint32_t b, uint32_t nb)
+// On-axis Polyakov correlator: for the separations r0 .. r0+kCorrGroup-1
+// that do not exceed rmax, sum_x L(x)(L(x+r e_x) + L(x+r e_y) + L(x+r e_z));
+// block b of nb writes its partial for r to partials[(r-1) nb + b]
+// (column r-1).  Each site's L(x) is loaded once for the whole group.
+__device__ __forceinline__ void polycorr_body(const double *Lfield, const Geom &g, double *partials, uint32_t r0,
+                                              uint32_t rmax, uint32_t b, uint32_t nb)
 {
-    __shared__ double lds[kBlock / 64][1];
+    __shared__ double lds[kBlock / 64][kCorrGroup];
     const uint32_t nx = (uint32_t)g.n[0], ny = (uint32_t)g.n[1], nz = (uint32_t)g.n[2];
-    double acc[1] = {0.0};
+    const uint32_t nr = rmax - r0 + 1u < kCorrGroup ? rmax - r0 + 1u : kCorrGroup;
+    double acc[kCorrGroup];
+#pragma unroll
+    for (uint32_t j = 0; j < kCorrGroup; ++j)
+        acc[j] = 0.0;
     for (uint32_t sp = b * kBlock + threadIdx.x; sp < g.vs; sp += nb * kBlock) {
         const uint32_t yz = fdiv(sp, g.div_nx);
         const uint32_t x = sp - yz * nx;
         const uint32_t z = fdiv(yz, g.div_ny);
         const uint32_t y = yz - z * ny;
-        const uint32_t xr = x + r, yr = y + r, zr = z + r;
-        const uint32_t xs = xr >= nx ? xr - nx : xr;
-        const uint32_t ys = yr >= ny ? yr - ny : yr;
-        const uint32_t zs = zr >= nz ? zr - nz : zr;
         const double L = Lfield[sp];
-        acc[0] += L * (Lfield[xs + nx * (y + ny * z)] + Lfield[x + nx * (ys + ny * z)] +
-                       Lfield[x + nx * (y + ny * zs)]);
+#pragma unroll
+        for (uint32_t j = 0; j < kCorrGroup; ++j) {
+            if (j < nr) {
+                const uint32_t r = r0 + j; // r <= min(Nx,Ny,Nz)/2: one wrap at most
+                const uint32_t xr = x + r, yr = y + r, zr = z + r;
+                const uint32_t xs = xr >= nx ? xr - nx : xr;
+                const uint32_t ys = yr >= ny ? yr - ny : yr;
+                const uint32_t zs = zr >= nz ? zr - nz : zr;
+                acc[j] += L * (Lfield[xs + nx * (y + ny * z)] + Lfield[x + nx * (ys + ny * z)] +
+                               Lfield[x + nx * (y + ny * zs)]);
+            }
+        }
     }
-    block_sum<1>(acc, lds);
+    block_sum<kCorrGroup>(acc, lds);
     if (threadIdx.x == 0)
-        partials[(size_t)(r - 1u) * nb + b] = acc[0];
+        for (uint32_t j = 0; j < nr; ++j)
+            partials[(size_t)(r0 + j - 1u) * nb + b] = acc[j];
 }
 
-// Separation r = blockIdx.y + 1.
-__global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, Geom g, double *partials)
+// Separation group blockIdx.y: r0 = kCorrGroup * blockIdx.y + 1.
+__global__ __launch_bounds__(kBlock) void polycorr_kernel(const double *Lfield, Geom g, double *partials,
+                                                           uint32_t rmax)
 {
-    polycorr_body(Lfield, g, partials, blockIdx.y + 1u, blockIdx.x, gridDim.x);
+    polycorr_body(Lfield, g, partials, kCorrGroup * blockIdx.y + 1u, rmax, blockIdx.x, gridDim.x);
 }
 
 // *out = scale * sum_b col[b], b < nblk, in a fixed order (one block).
@@ -264,13 +277,13 @@ __global__ __launch_bounds__(kBlock) void polyakov_batch_kernel(const BatchEntry
     polyakov_body<T>(U, e.g, e.lfield, e.poly_part, blockIdx.x - e.pblock0, e.pnblk);
 }
 
-// A lattice's rmax * cnblk blocks: separation r = local / cnblk + 1.
+// A lattice's corr_groups(rmax) * cnblk blocks: separation group local / cnblk.
 __global__ __launch_bounds__(kBlock) void polycorr_batch_kernel(const BatchEntry *tab, int count)
 {
     const BatchEntry &e = tab[find_entry_index<&BatchEntry::cblock0>(tab, count, blockIdx.x)];
     const uint32_t local = blockIdx.x - e.cblock0;
-    const uint32_t rm1 = local / e.cnblk;
-    polycorr_body(e.lfield, e.g, e.corr_part, rm1 + 1u, local - rm1 * e.cnblk, e.cnblk);
+    const uint32_t grp = local / e.cnblk;
+    polycorr_body(e.lfield, e.g, e.corr_part, kCorrGroup * grp + 1u, e.rmax, local - grp * e.cnblk, e.cnblk);
 }
 
 // One block per output: lattice j's columns 0, 1 (mean L, mean |L|) go to
@@ -349,7 +362,7 @@ void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, do
     colsum_kernel<<<2, kBlock, 0, st>>>(pp, w.nblk_poly, 1.0 / (double)g.vs, d_out);
     if (d_corr && w.rmax > 0) {
         double *cp = reinterpret_cast<double *>(a.work + w.off_corr);
-        polycorr_kernel<<<dim3(w.nblk_corr, (uint32_t)w.rmax), kBlock, 0, st>>>(Lf, g, cp);
+        polycorr_kernel<<<dim3(w.nblk_corr, corr_groups(w.rmax)), kBlock, 0, st>>>(Lf, g, cp, (uint32_t)w.rmax);
         colsum_kernel<<<w.rmax, kBlock, 0, st>>>(cp, w.nblk_corr, 1.0 / (3.0 * (double)g.vs), d_corr);
     }
 }
@@ -383,7 +396,7 @@ void launch_measure(const LaunchArgs &a, const WorkLayout &w, double *d_plaq, do
     colsum_kernel<<<2, kBlock, 0, st>>>(pm + (size_t)6 * w.nblk_meas, w.nblk_meas, 1.0 / (double)g.vs, d_poly);
     if (d_corr && w.rmax > 0) {
         double *cp = reinterpret_cast<double *>(a.work + w.off_corr);
-        polycorr_kernel<<<dim3(w.nblk_corr, (uint32_t)w.rmax), kBlock, 0, st>>>(Lf, g, cp);
+        polycorr_kernel<<<dim3(w.nblk_corr, corr_groups(w.rmax)), kBlock, 0, st>>>(Lf, g, cp, (uint32_t)w.rmax);
         colsum_kernel<<<w.rmax, kBlock, 0, st>>>(cp, w.nblk_corr, 1.0 / (3.0 * (double)g.vs), d_corr);
     }
 }
