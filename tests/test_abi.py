@@ -85,6 +85,7 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     for beta in (float("nan"), float("inf"), -0.5):
         assert L.su2_heatbath_sweep(ok, beta, 1, 0, s) == su2.SU2_EINVAL
         assert L.su2_heatbath_halfsweep(ok, beta, 1, 0, 0, 0, s) == su2.SU2_EINVAL
+        assert L.su2_heatbath_sweep_measured(ok, beta, 1, 0, 0x30000, s) == su2.SU2_EINVAL
     # class indices
     assert L.su2_heatbath_halfsweep(ok, 2.3, 1, 0, 4, 0, s) == su2.SU2_EINVAL
     assert L.su2_heatbath_halfsweep(ok, 2.3, 1, 0, 0, 2, s) == su2.SU2_EINVAL
@@ -96,6 +97,12 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     assert L.su2_plaquette(ok, 0x30004, s) == su2.SU2_EALIGN
     assert L.su2_polyakov(ok, None, None, s) == su2.SU2_EINVAL
     assert L.su2_polyakov(ok, 0x30000, 0x30003, s) == su2.SU2_EALIGN
+    assert L.su2_heatbath_sweep_measured(ok, 2.3, 1, 0, None, s) == su2.SU2_EINVAL
+    assert L.su2_heatbath_sweep_measured(ok, 2.3, 1, 0, 0x30004, s) == su2.SU2_EALIGN
+    assert L.su2_overrelax_measured(ok, 1, None, s) == su2.SU2_EINVAL
+    assert L.su2_overrelax_measured(ok, 1, 0x30004, s) == su2.SU2_EALIGN
+    assert L.su2_overrelax_measured(ok, -1, 0x30000, s) == su2.SU2_EINVAL
+    assert L.su2_overrelax_measured(by(_desc(su2, wb=need - 1)), 1, 0x30000, s) == su2.SU2_EWORK
     assert L.su2_get_flags(ok, None, s) == su2.SU2_EINVAL
     assert L.su2_get_flags(ok, 0x30002, s) == su2.SU2_EALIGN
     # tile: a positive strip width must divide Nz
