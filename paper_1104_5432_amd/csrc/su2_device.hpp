@@ -736,8 +736,8 @@ __device__ __forceinline__ void reserve_lds_for_residency()
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic reductions: wave64 shuffles, then an LDS tree over the
-// block's waves in a fixed order.
+// Deterministic reductions: a fixed-order wave64 sum (DPP lane moves and
+// scalar read-out), then the block's waves through LDS in a fixed order.
 // ---------------------------------------------------------------------------
 // A DPP lane move of a double within rows of 16 lanes (two 32-bit moves;
 // every source lane of the controls used below is valid).
