@@ -5,10 +5,31 @@ the jackknife, and the property the renormalisation exists for.
 
 The absolute sigma(T) values of the paper stay unpinned: they need its
 configurations.  What is pinned is the procedure."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_1104_5432_amd import analysis as an
+
+# the fit parameters the paper prints (Sec. 2.2), with their citations
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "finite_temperature_fits.json")))
+
+
+def test_paper_constants_are_the_printed_ones():
+    z = GOLDEN["renormalisation_z"]
+    assert an.PAPER_Z_A == z["A"] and an.PAPER_Z_B == z["B"]
+    # the renormalisation factor per time slice at the edge of the fit's
+    # stated range, from the printed A, B: Z(1.3) = exp(0.0637*1.3 + 0.0731*1.69)
+    assert an.renormalization_z(4.0 / z["g2_max"]) == pytest.approx(np.exp(z["A"] * 1.3 + z["B"] * 1.3 ** 2),
+                                                                     rel=1e-14)
+    # sigma(T = Tc) from the printed sqrt-ansatz parameters: a sqrt(1 - b)
+    q = GOLDEN["sigma_sqrt_ansatz"]
+    assert an.sigma_ansatz_sqrt(np.array([1.0]), q["a"], q["b"])[0] == pytest.approx(0.6976 * np.sqrt(0.001),
+                                                                                     rel=1e-12)
+    c = GOLDEN["sigma_critical_ansatz"]
+    assert an.sigma_ansatz_critical(np.array([1.0]), c["a"], c["b"], c["nu"])[0] == 0.0
 
 
 def test_renormalisation_removes_the_nt_dependence():
@@ -16,10 +37,11 @@ def test_renormalisation_removes_the_nt_dependence():
     # of a function of T alone, the renormalised loop is the same for every
     # Nt; with the paper's A, B at g^2 = 4/beta.
     f_T = 0.4
+    A, B = GOLDEN["renormalisation_z"]["A"], GOLDEN["renormalisation_z"]["B"]
     for beta in (2.4, 2.6, 3.2, 4.0):
         z = an.renormalization_z(beta)
         g2 = 4.0 / beta
-        assert z == pytest.approx(np.exp(0.0637 * g2 + 0.0731 * g2 ** 2), rel=1e-15)
+        assert z == pytest.approx(np.exp(A * g2 + B * g2 ** 2), rel=1e-15)
         lr = [an.renormalized_polyakov(f_T * z ** -nt, beta, nt) for nt in (4, 6, 8, 12)]
         assert np.allclose(lr, f_T, rtol=1e-13)
     # weak coupling: Z -> 1
@@ -83,9 +105,11 @@ def test_string_tension_from_per_sweep_correlators():
     assert perr[2] < 0.01
 
 
-@pytest.mark.parametrize("ansatz,truth", [("sqrt", (0.6976, 0.9990)), ("critical", (1.5541, -0.5122))])
-def test_sigma_of_t_ansatz_fits_recover_the_papers_parameters(ansatz, truth):
+@pytest.mark.parametrize("ansatz", ["sqrt", "critical"])
+def test_sigma_of_t_ansatz_fits_recover_the_papers_parameters(ansatz):
     # data generated from the paper's fitted parameters are fitted back
+    g = GOLDEN["sigma_sqrt_ansatz" if ansatz == "sqrt" else "sigma_critical_ansatz"]
+    truth = (g["a"], g["b"])
     t = np.linspace(0.3, 0.95, 12)
     f = an.sigma_ansatz_sqrt if ansatz == "sqrt" else an.sigma_ansatz_critical
     s = f(t, *truth)
