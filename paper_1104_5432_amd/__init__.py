@@ -297,7 +297,8 @@ def su2_batch_polyakov(batch, poly=None, corr=None, with_corr=True, stream=None)
     [count, stride] float64 or None); row j of corr holds C(r), r = 1..
     min(Nx,Ny,Nz)/2 of lattice j, and is left untouched beyond."""
     dev = batch.lattices[0].device
-    stride = max(min(lat.n[:3]) // 2 for lat in batch.lattices)
+    rmax = max(min(lat.n[:3]) // 2 for lat in batch.lattices)
+    stride = rmax
     if poly is None:
         poly = torch.empty((batch.count, 2), dtype=torch.float64, device=dev)
     if with_corr and corr is None:
@@ -305,8 +306,10 @@ def su2_batch_polyakov(batch, poly=None, corr=None, with_corr=True, stream=None)
     if poly.shape != (batch.count, 2) or poly.dtype != torch.float64 or not poly.is_contiguous():
         raise ValueError("poly must be a contiguous float64 tensor of shape (count, 2)")
     if corr is not None:
-        if corr.dim() != 2 or corr.shape[0] != batch.count or corr.dtype != torch.float64 or corr.stride(1) != 1:
-            raise ValueError("corr must be a float64 tensor of shape (count, stride) with unit column stride")
+        if (corr.dim() != 2 or corr.shape[0] != batch.count or corr.shape[1] < rmax or corr.dtype != torch.float64
+                or corr.stride(1) != 1):
+            raise ValueError("corr must be a float64 tensor of shape (count, >= max min(Nx,Ny,Nz)/2) with unit "
+                             "column stride")
         stride = corr.stride(0)
     _check(lib.su2_batch_polyakov(batch.descs, batch.count, batch.table.data_ptr(), poly.data_ptr(),
                                   corr.data_ptr() if corr is not None else None, int(stride), _stream(stream)))

@@ -175,3 +175,22 @@ def test_layout_conversion_matches_documented_layout(su2, prec):
             d2 = lat.links.view(torch.float64).view(-1, 2)
             v = np.concatenate([d2[(2 * q) * half + cb].numpy(), d2[(2 * q + 1) * half + cb].numpy()])
         assert np.max(np.abs(v - U[t, z, y, x, mu])) <= tol
+
+
+def test_batch_polyakov_binding_checks_its_tensors(su2):
+    # rejected in the binding before any library call (host tensors only)
+    import torch
+    lats = [su2.Lattice((8, 8, 8, 4), "f32", device="cpu", lattice_id=0),
+            su2.Lattice((4, 4, 4, 6), "f32", device="cpu", lattice_id=1)]
+    batch = su2.Batch(lats, [2.3, 2.4])
+    good_poly = torch.zeros((2, 2), dtype=torch.float64)
+    for poly in (torch.zeros((2, 3), dtype=torch.float64), torch.zeros((2, 2), dtype=torch.float32),
+                 torch.zeros((2, 4), dtype=torch.float64)[:, ::2]):
+        with pytest.raises(ValueError):
+            su2.su2_batch_polyakov(batch, poly=poly, with_corr=False)
+    for corr in (torch.zeros((2, 3), dtype=torch.float64),          # rmax of 8^3 x 4 is 4
+                 torch.zeros((3, 4), dtype=torch.float64),
+                 torch.zeros((2, 4), dtype=torch.float32),
+                 torch.zeros((2, 8), dtype=torch.float64)[:, ::2]):
+        with pytest.raises(ValueError):
+            su2.su2_batch_polyakov(batch, poly=good_poly, corr=corr)
