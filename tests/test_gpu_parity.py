@@ -201,6 +201,29 @@ def test_fp32_halfsweep_close_to_oracle(su2):
     assert np.mean(d > 5e-5) <= 1e-3, np.sort(d.ravel())[-5:]
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("beta", [0.0, 1e6])
+def test_heatbath_degenerate_couplings_match_oracle(su2, prec, beta):
+    # beta = 0 (flat weight: the Creutz branch with alpha < 1e-8, Haar links)
+    # and beta = 1e6 (Kennedy-Pendleton with lambda^2 ~ 1e-7), one class of a
+    # thermalised configuration, per link against the oracle
+    n, seed = (8, 6, 10, 8), 31
+    U0 = oracle.init_hot(n, seed)
+    for s in range(2):
+        oracle.heatbath_sweep(n, U0, 2.3, seed, s)
+    lat = _lat(su2, n, prec, U0)
+    ref = su2.to_canonical(lat).numpy()            # the start the GPU holds
+    oracle.heatbath_halfsweep(n, ref, beta, seed, 2, 2, 1)
+    su2.su2_heatbath_halfsweep(lat, beta, seed, 2, 2, 1)
+    _sync()
+    d = np.max(np.abs(su2.to_canonical(lat).numpy() - ref), axis=-1)
+    if prec == "f64":
+        assert d.max() <= 1e-12
+    else:
+        assert np.mean(d > 5e-5) <= 1e-3 and np.median(d) < 1e-6, np.sort(d.ravel())[-5:]
+    assert _flags(su2, lat) == 0
+
+
 # ---------------------------------------------------------------------------
 # overrelaxation
 # ---------------------------------------------------------------------------

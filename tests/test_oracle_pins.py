@@ -301,6 +301,59 @@ def test_single_link_sampler_law(beta):
     assert stats.kstest(v[:, 2], "uniform", args=(-1, 2)).pvalue > 1e-4
 
 
+def test_heatbath_at_zero_beta_draws_haar_links():
+    # beta = 0: the local weight is flat, so an updated link is Haar
+    # distributed whatever its staple and its old value (the Creutz branch
+    # with alpha < 1e-8 draws x0 uniform and accepts with sqrt(1 - x0^2))
+    n = (16, 16, 16, 8)
+    U = oracle.init_hot(n, 77)
+    oracle.heatbath_sweep(n, U, 2.3, 77, 0)          # a non-trivial configuration
+    old = U.copy()
+    flags = oracle.heatbath_halfsweep(n, U, 0.0, 77, 1, 1, 1)
+    assert flags == 0
+    flat, prev = U.reshape(-1, 4, 4), old.reshape(-1, 4, 4)
+    par = np.add.reduce(np.indices((n[3], n[2], n[1], n[0])), axis=0).reshape(-1) % 2
+    q = flat[par == 1, 1]
+    N = q.shape[0]
+    assert np.max(np.abs((q * q).sum(1) - 1.0)) < 1e-15
+    for k in range(4):
+        assert stats.kstest(q[:, k], stats_util.haar_a0_cdf).pvalue > 1e-4
+    assert np.all(np.abs(q.mean(0)) < 5 * np.sqrt(0.25 / N))
+    # independent of the link it replaces: <Tr(U_new U_old^+)/2> = 0
+    tr = (q * prev[par == 1, 1]).sum(1)
+    assert abs(tr.mean()) < 5 * np.sqrt(0.25 / N)
+    # nothing else moved
+    assert np.array_equal(flat[par == 0], prev[par == 0])
+    assert np.array_equal(flat[:, [0, 2, 3]], prev[:, [0, 2, 3]])
+
+
+def test_heatbath_at_huge_beta_stays_exact():
+    # beta = 1e6 (alpha ~ 1e6-1e7): Kennedy-Pendleton with lambda^2 ~ 1e-7;
+    # 1 - x0 = 2 lambda^2 is formed without cancellation, so its mean over
+    # the updated links matches 1 - I2(alpha)/I1(alpha) ~ 3/(2 alpha), and
+    # every link stays finite and unit
+    n = (16, 16, 16, 8)
+    beta = 1e6
+    U = oracle.init_cold(n)
+    assert oracle.heatbath_halfsweep(n, U, beta, 5, 0, 0, 0) == 0
+    flat = U.reshape(-1, 4, 4)
+    par = np.add.reduce(np.indices((n[3], n[2], n[1], n[0])), axis=0).reshape(-1) % 2
+    upd = flat[par == 0, 0]
+    assert np.all(np.isfinite(upd)) and np.max(np.abs((upd * upd).sum(1) - 1.0)) < 1e-15
+    alpha = 6 * beta                                  # cold start: k = 6
+    one_minus = 1.0 - upd[:, 0]
+    expect = 1.0 - special.ive(2, alpha) / special.ive(1, alpha)
+    assert abs(expect - 1.5 / alpha) < 1e-3 * expect
+    # the vector part: |x|^2 = 1 - x0^2 to the rounding of x0 (ulp(1) ~ 1.1e-16)
+    xv = (upd[:, 1:] ** 2).sum(1)
+    assert np.max(np.abs(xv - one_minus * (2.0 - one_minus))) < 4e-16
+    # the law: the mean of 1 - x0, from |x|^2 / 2 = 2 lambda^2 (1 - lambda^2),
+    # which is free of the rounding of x0 near 1
+    N = xv.size
+    assert abs(xv.mean() / 2 - expect) < 5 * (xv / 2).std() / np.sqrt(N)
+    assert abs(one_minus.mean() - expect) < 5 * one_minus.std() / np.sqrt(N)
+
+
 @pytest.mark.parametrize("beta,mu,p", [(2.3, 2, 1), (0.4, 3, 0), (1.0, 1, 1)])
 def test_heatbath_pit_at_equilibrium(beta, mu, p):
     # After a half-sweep of class (mu, p) the staples of that class are
