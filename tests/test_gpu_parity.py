@@ -253,6 +253,29 @@ def test_overrelax_matches_oracle(su2, n):
     assert _maxdiff(su2.to_canonical(lat).numpy(), ref) <= 1e-10
 
 
+@pytest.mark.parametrize("n", [(8, 8, 8, 8), (6, 4, 10, 8)])
+def test_fp32_overrelax_close_to_oracle(su2, n):
+    # FP32 links: every class from the same FP32-rounded configuration
+    # against the FP64 oracle on that configuration.  The map is
+    # deterministic, so the bound is the rounding of the FP32 staple (six
+    # products of three links) and of the reflection: 2e-6 per link.
+    U0 = oracle.init_hot(n, 45)
+    for s in range(2):
+        oracle.heatbath_sweep(n, U0, 2.3, 45, s)
+    lat = _lat(su2, n, "f32", U0)
+    for mu in range(4):
+        for par in range(2):
+            start = su2.to_canonical(lat).numpy()
+            ref = start.copy()
+            oracle.overrelax_halfsweep(n, ref, mu, par)
+            su2.su2_overrelax_halfsweep(lat, mu, par)
+            _sync()
+            got = su2.to_canonical(lat).numpy()
+            assert _maxdiff(got, ref) <= 2e-6, (mu, par, _maxdiff(got, ref))
+            # FP32 writes are normalised
+            assert np.max(np.abs((got * got).sum(-1) - 1.0)) <= 3e-7
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 2e-5)])
 def test_overrelax_invariants_on_gpu(su2, prec, tol):
     n = (8, 8, 8, 8)
