@@ -169,3 +169,37 @@ def test_graph_replay_matches_eager(su2, prec):
             assert torch.equal(p, pe) and torch.equal(q, qe) and torch.equal(c[:len(ce)], ce), (s, lat_g.n)
         for j, (q, c) in enumerate(zip(poly, corr)):
             assert torch.equal(bpoly[j], q) and torch.equal(bcorr[j, :c.numel()], c), (s, j)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_graph_replay_of_the_measured_step(su2, prec):
+    # the benchmark's step in a captured graph: heat bath (a batch of one,
+    # sweep index from device memory), overrelaxation whose last sweep takes
+    # the plaquette, Polyakov loop and correlator; every replay equals the
+    # same calls made eagerly, with eager work and synchronisations between
+    seed, n = 808, (8, 8, 8, 4)
+    g_lat = su2.Lattice(n, prec, device="cuda", lattice_id=3)
+    e_lat = su2.Lattice(n, prec, device="cuda", lattice_id=3)
+    for lat in (g_lat, e_lat):
+        su2.su2_init_hot(lat, seed)
+    g_batch = su2.Batch([g_lat], [2.4])
+    d_sweep = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plaq = torch.zeros(7, dtype=torch.float64, device="cuda")
+    poly = torch.zeros(2, dtype=torch.float64, device="cuda")
+    corr = torch.zeros(min(n[:3]) // 2, dtype=torch.float64, device="cuda")
+    _sync()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        su2.su2_batch_heatbath_sweep(g_batch, seed, d_sweep=d_sweep)
+        su2.su2_overrelax_measured(g_lat, 3, plaq)
+        su2.su2_polyakov(g_lat, poly, corr)
+        su2.su2_sweep_advance(d_sweep)
+    _sync()
+    for s in range(4):
+        graph.replay()
+        su2.su2_heatbath_sweep(e_lat, 2.4, seed, s)
+        pe = su2.su2_overrelax_measured(e_lat, 3)
+        qe, ce = su2.su2_polyakov(e_lat)
+        _sync()
+        assert torch.equal(g_lat.links, e_lat.links), s
+        assert torch.equal(plaq, pe) and torch.equal(poly, qe) and torch.equal(corr, ce), s
