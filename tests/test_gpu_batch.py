@@ -203,3 +203,32 @@ def test_graph_replay_of_the_measured_step(su2, prec):
         _sync()
         assert torch.equal(g_lat.links, e_lat.links), s
         assert torch.equal(plaq, pe) and torch.equal(poly, qe) and torch.equal(corr, ce), s
+
+
+def test_many_lattice_batch_matches_single_lattices(su2):
+    # 130 lattices: the block -> lattice lookup takes three rounds of wave
+    # ballots (64 entries each); tiny and ragged shapes, one block each
+    shapes = [(2, 2, 2, 2), (4, 2, 2, 2), (2, 4, 6, 2), (4, 4, 4, 4)]
+    seed, count = 55, 130
+    batched, single, betas = [], [], []
+    for j in range(count):
+        n = shapes[j % len(shapes)]
+        for group in (batched, single):
+            lat = su2.Lattice(n, "f32", device="cuda", lattice_id=j)
+            su2.su2_init_hot(lat, seed)
+            group.append(lat)
+        betas.append(1.5 + j / count)
+    batch = su2.Batch(batched, betas)
+    for s in range(2):
+        su2.su2_batch_heatbath_sweep(batch, seed, sweep=s)
+        su2.su2_batch_overrelax(batch, 1)
+        for lat, beta in zip(single, betas):
+            su2.su2_heatbath_sweep(lat, beta, seed, s)
+            su2.su2_overrelax(lat, 1)
+    poly, corr = su2.su2_batch_polyakov(batch)
+    _sync()
+    for j, (a, b) in enumerate(zip(batched, single)):
+        assert torch.equal(a.links, b.links), j
+        q, c = su2.su2_polyakov(b)
+        _sync()
+        assert torch.equal(poly[j], q) and torch.equal(corr[j, :c.numel()], c), j
