@@ -21,7 +21,7 @@ def test_more_than_one_gpu_exits_with_a_message():
 def test_help_lists_the_workloads():
     r = _run("--help")
     assert r.returncode == 0
-    for w in ("single", "scan", "learned", "precision", "--autotune", "--tile-y"):
+    for w in ("single", "scan", "learned", "precision", "--autotune", "--tile-y", "--fused-plaquette"):
         assert w in r.stdout
 
 
