@@ -44,6 +44,7 @@ def lib():
             "or_init_cold": (None, [i4, dp]),
             "or_init_hot": (None, [i4, dp, u64, u32]),
             "or_heatbath_halfsweep": (u32, [i4, dp, dbl, u64, u32, i32, i32, u32]),
+            "or_heatbath_halfsweep_f32": (u32, [i4, dp, dbl, u64, u32, i32, i32, u32]),
             "or_heatbath_sweep": (u32, [i4, dp, dbl, u64, u32, u32]),
             "or_overrelax_halfsweep": (u32, [i4, dp, i32, i32]),
             "or_overrelax_sweep": (u32, [i4, dp]),
@@ -160,6 +161,16 @@ def init_hot(n, seed, lattice_id=0):
 def heatbath_halfsweep(n, U, beta, seed, sweep, mu, parity, lattice_id=0):
     _check_links(n, U)
     return lib().or_heatbath_halfsweep(_dims(n), _dp(U), beta, seed, sweep, mu, parity, lattice_id)
+
+
+def heatbath_halfsweep_f32(n, U, beta, seed, sweep, mu, parity, lattice_id=0):
+    """The half-sweep with single-precision links (U must hold FP32-representable
+    values; the updated links are FP32 values): every accept/reject decision
+    in the precisions of the single-precision path."""
+    _check_links(n, U)
+    if not np.array_equal(U.astype(np.float32).astype(np.float64), U):
+        raise ValueError("U must hold values representable in single precision")
+    return lib().or_heatbath_halfsweep_f32(_dims(n), _dp(U), beta, seed, sweep, mu, parity, lattice_id)
 
 
 def heatbath_sweep(n, U, beta, seed, sweep, lattice_id=0):

@@ -320,6 +320,163 @@ uint32_t or_heatbath_halfsweep(const int n[4], double *U, double beta, uint64_t 
     return flags;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Heat bath for single-precision links.  The same chain step with the       */
+/* precisions of the single-precision path (Sec. 2.1 runs both precisions):  */
+/* links, staple and the new link in single precision; uniforms from the top */
+/* 23 bits of the even Philox words; of a Kennedy-Pendleton attempt the two  */
+/* logarithms and the cosine in single precision, while lambda^2, the accept */
+/* test, x0 = 1 - 2 lambda^2 and |x| are formed in double (lambda^2 carries  */
+/* 1 - x0, so x0 near 1 loses nothing); the Creutz branch in double; the     */
+/* direction in single precision; the new link renormalised in single        */
+/* precision.  Its use is to take every accept/reject decision in the same   */
+/* precisions as a single-precision implementation, so that the two agree    */
+/* link by link instead of up to decisions that flip between 23-bit and      */
+/* 52-bit arithmetic.  Single-precision elementary functions are taken as    */
+/* the double-precision value rounded to single precision.                   */
+/* ------------------------------------------------------------------------ */
+static void qmul_f(const float a[4], const float b[4], float out[4])
+{
+    float r0 = a[0] * b[0] - (a[1] * b[1] + a[2] * b[2] + a[3] * b[3]);
+    float r1 = a[0] * b[1] + b[0] * a[1] - (a[2] * b[3] - a[3] * b[2]);
+    float r2 = a[0] * b[2] + b[0] * a[2] - (a[3] * b[1] - a[1] * b[3]);
+    float r3 = a[0] * b[3] + b[0] * a[3] - (a[1] * b[2] - a[2] * b[1]);
+    out[0] = r0;
+    out[1] = r1;
+    out[2] = r2;
+    out[3] = r3;
+}
+
+static void link_f(const double *U, int64_t site, int mu, int dagger, float q[4])
+{
+    const double *l = link(U, site, mu);
+    q[0] = (float)l[0];
+    for (int k = 1; k < 4; ++k)
+        q[k] = dagger ? -(float)l[k] : (float)l[k];
+}
+
+static void staple_f32(const int n[4], const double *U, int64_t site, int mu, float V[4])
+{
+    V[0] = V[1] = V[2] = V[3] = 0.0f;
+    int64_t xp = or_neighbor(n, site, mu, +1);
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu)
+            continue;
+        float a[4], b[4], c[4], t[4], s[4];
+        int64_t xn = or_neighbor(n, site, nu, +1);
+        link_f(U, xp, nu, 0, a);
+        link_f(U, xn, mu, 1, b);
+        link_f(U, site, nu, 1, c);
+        qmul_f(a, b, t);
+        qmul_f(t, c, s);
+        for (int k = 0; k < 4; ++k)
+            V[k] += s[k];
+        int64_t xm = or_neighbor(n, site, nu, -1);
+        int64_t xpm = or_neighbor(n, xp, nu, -1);
+        link_f(U, xpm, nu, 1, a);
+        link_f(U, xm, mu, 1, b);
+        link_f(U, xm, nu, 0, c);
+        qmul_f(a, b, t);
+        qmul_f(t, c, s);
+        for (int k = 0; k < 4; ++k)
+            V[k] += s[k];
+    }
+}
+
+static void draw_f32(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, float *ua, float *ub)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    or_philox4x32_10(ctr, key, r);
+    *ua = or_u01_f32(r[0]);
+    *ub = or_u01_f32(r[2]);
+}
+
+static uint32_t heatbath_link_f32(double Ulink[4], const float V[4], double beta, uint64_t seed, uint32_t site,
+                                  uint32_t c1, uint32_t sweep)
+{
+    float k = sqrtf(V[0] * V[0] + V[1] * V[1] + V[2] * V[2] + V[3] * V[3]);
+    if (!isfinite(k))
+        return OR_FLAG_NONFINITE;
+    float Vhat[4] = {1.0f, 0.0f, 0.0f, 0.0f};
+    if (k > 0.0f) {
+        float inv = 1.0f / k;
+        for (int j = 0; j < 4; ++j)
+            Vhat[j] = V[j] * inv;
+    }
+    double alpha = beta * (double)k;
+    double inv2a = 1.0 / (2.0 * (alpha > 1.0 ? alpha : 1.0));
+
+    double x0 = 0.0, xlen = 0.0;
+    int accepted = 0;
+    for (uint32_t a = 0; a < OR_MAX_ATTEMPTS && !accepted; ++a) {
+        if (alpha >= 2.0) {
+            float u1, u2, u3, u4;
+            draw_f32(seed, site, c1, sweep, 4u * a + 0u, &u1, &u2);
+            draw_f32(seed, site, c1, sweep, 4u * a + 1u, &u3, &u4);
+            float c = (float)cos(2.0 * OR_PI * (double)u2);
+            float l1 = (float)log((double)u1), l3 = (float)log((double)u3);
+            double lam2 = -((double)l1 + (double)(c * c) * (double)l3) * inv2a;
+            if (lam2 <= 1.0 && (double)u4 * (double)u4 <= 1.0 - lam2) {
+                x0 = 1.0 - 2.0 * lam2;
+                xlen = 2.0 * sqrt(lam2 * (1.0 - lam2));
+                accepted = 1;
+            }
+        } else {
+            float f1, f2;
+            draw_f32(seed, site, c1, sweep, 4u * a + 0u, &f1, &f2);
+            double u1 = f1, u2 = f2, t;
+            if (alpha < 1e-8) {
+                t = 2.0 * u1 - 1.0;
+            } else {
+                double e = exp(-2.0 * alpha);
+                t = 1.0 + log(e + u1 * (1.0 - e)) / alpha;
+            }
+            if (u2 * u2 <= 1.0 - t * t) {
+                x0 = t;
+                double sq = 1.0 - t * t;
+                xlen = sqrt(sq > 0.0 ? sq : 0.0);
+                accepted = 1;
+            }
+        }
+    }
+    if (!accepted)
+        return OR_FLAG_CAP;
+
+    float u5, u6;
+    draw_f32(seed, site, c1, sweep, 2u, &u5, &u6);
+    float cth = 2.0f * u5 - 1.0f;
+    float sq = 1.0f - cth * cth;
+    float sth = sqrtf(sq > 0.0f ? sq : 0.0f);
+    float cph = (float)cos(2.0 * OR_PI * (double)u6), sph = (float)sin(2.0 * OR_PI * (double)u6);
+    float xl = (float)xlen;
+    float W[4] = {(float)x0, xl * sth * cph, xl * sth * sph, xl * cth};
+    float Vd[4] = {Vhat[0], -Vhat[1], -Vhat[2], -Vhat[3]}, Un[4];
+    qmul_f(W, Vd, Un);
+    float nrm = 1.0f / sqrtf(Un[0] * Un[0] + Un[1] * Un[1] + Un[2] * Un[2] + Un[3] * Un[3]);
+    for (int j = 0; j < 4; ++j)
+        Ulink[j] = (double)(Un[j] * nrm);
+    return 0;
+}
+
+uint32_t or_heatbath_halfsweep_f32(const int n[4], double *U, double beta, uint64_t seed, uint32_t sweep, int mu,
+                                   int parity, uint32_t lattice_id)
+{
+    int64_t vol = or_volume(n);
+    uint32_t c1 = (uint32_t)(mu + 4 * 1 + 16 * lattice_id);
+    uint32_t flags = 0;
+#pragma omp parallel for schedule(static) reduction(| : flags)
+    for (int64_t i = 0; i < vol; ++i) {
+        if (or_parity(n, i) != parity)
+            continue;
+        float V[4];
+        staple_f32(n, U, i, mu, V);
+        flags |= heatbath_link_f32(U + (i * 4 + mu) * 4, V, beta, seed, (uint32_t)i, c1, sweep);
+    }
+    return flags;
+}
+
 /* A sweep: mu = x, y, z, t in turn, even sites before odd sites. */
 uint32_t or_heatbath_sweep(const int n[4], double *U, double beta, uint64_t seed,
                            uint32_t sweep, uint32_t lattice_id)

@@ -72,6 +72,11 @@ uint32_t or_heatbath_halfsweep(const int n[4], double *U, double beta, uint64_t 
                                uint32_t sweep, int mu, int parity, uint32_t lattice_id);
 uint32_t or_heatbath_sweep(const int n[4], double *U, double beta, uint64_t seed,
                            uint32_t sweep, uint32_t lattice_id);
+/* The heat-bath half-sweep with single-precision links: U must hold values
+ * representable in single precision and receives single-precision results;
+ * the precisions of each step are listed in su2_oracle.c. */
+uint32_t or_heatbath_halfsweep_f32(const int n[4], double *U, double beta, uint64_t seed,
+                                   uint32_t sweep, int mu, int parity, uint32_t lattice_id);
 uint32_t or_overrelax_halfsweep(const int n[4], double *U, int mu, int parity);
 uint32_t or_overrelax_sweep(const int n[4], double *U);
 

@@ -354,6 +354,39 @@ def test_heatbath_at_huge_beta_stays_exact():
     assert abs(one_minus.mean() - expect) < 5 * one_minus.std() / np.sqrt(N)
 
 
+@pytest.mark.parametrize("beta", [0.3, 2.3])
+def test_single_precision_heatbath_law_and_agreement(beta):
+    # The oracle's single-precision half-sweep (decisions in the precisions
+    # of the FP32 path) samples the same law -- KS against the exact density
+    # from a cold start (Creutz at alpha = 1.8, Kennedy-Pendleton at 13.8) --
+    # and, from an FP32-rounded thermalised configuration, agrees with the
+    # FP64 half-sweep link by link to FP32 rounding except where a decision
+    # flips between 23-bit and 52-bit uniforms.
+    n = (16, 16, 16, 8)
+    U = oracle.init_cold(n)
+    assert oracle.heatbath_halfsweep_f32(n, U, beta, 4321, 0, 0, 0) == 0
+    assert np.array_equal(U.astype(np.float32).astype(np.float64), U)
+    par = np.add.reduce(np.indices((n[3], n[2], n[1], n[0])), axis=0).reshape(-1) % 2
+    upd = U.reshape(-1, 4, 4)[par == 0, 0]
+    assert np.max(np.abs((upd * upd).sum(1) - 1.0)) < 6e-7     # a few FP32 ulp
+    x0 = upd[:, 0]
+    alpha = 6 * beta
+    assert stats.kstest(x0, lambda w: stats_util.x0_cdf(np.full_like(w, alpha), w)).pvalue > 1e-4
+    mean = special.ive(2, alpha) / special.ive(1, alpha)
+    assert abs(x0.mean() - mean) < 5 * x0.std() / np.sqrt(x0.size)
+
+    m = (8, 8, 8, 8)
+    T = oracle.init_hot(m, 3)
+    for s in range(3):
+        oracle.heatbath_sweep(m, T, 2.3, 3, s)
+    T = T.astype(np.float32).astype(np.float64)
+    a, b = T.copy(), T.copy()
+    oracle.heatbath_halfsweep_f32(m, a, beta, 99, 4, 1, 0)
+    oracle.heatbath_halfsweep(m, b, beta, 99, 4, 1, 0)
+    d = np.max(np.abs(a - b), axis=-1)
+    assert np.mean(d > 5e-5) <= 1e-3 and np.median(d[d > 0]) < 1e-6
+
+
 @pytest.mark.parametrize("beta,mu,p", [(2.3, 2, 1), (0.4, 3, 0), (1.0, 1, 1)])
 def test_heatbath_pit_at_equilibrium(beta, mu, p):
     # After a half-sweep of class (mu, p) the staples of that class are
