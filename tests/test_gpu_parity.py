@@ -251,6 +251,30 @@ def test_fp32_heatbath_matches_single_precision_oracle(su2, n, beta):
     assert _flags(su2, lat) == 0
 
 
+@pytest.mark.parametrize("beta", [2.3, 6.0])
+def test_fp32_heatbath_chain_matches_single_precision_oracle(su2, beta):
+    # three chained FP32 heat-bath sweeps from the hot start against the
+    # oracle's single-precision chain: with every decision taken in the same
+    # precisions the chains stay together link by link.  A different
+    # decision would move a link by O(0.1); the FP32 rounding differences
+    # (~5e-7 after one class) grow through the chain to ~1.5e-5 after three
+    # sweeps from the hot start, so the bound is 1e-4.
+    n, seed = (8, 8, 8, 8), 1234
+    lat = _lat(su2, n, "f32")
+    su2.su2_init_hot(lat, seed)
+    _sync()
+    ref = su2.to_canonical(lat).numpy()
+    for s in range(3):
+        for mu in range(4):
+            for par in range(2):
+                assert oracle.heatbath_halfsweep_f32(n, ref, beta, seed, s, mu, par) == 0
+        su2.su2_heatbath_sweep(lat, beta, seed, s)
+    _sync()
+    d = np.max(np.abs(su2.to_canonical(lat).numpy() - ref), axis=-1)
+    assert d.max() <= 1e-4, np.sort(d.ravel())[-3:]
+    assert np.median(d) <= 1e-6
+
+
 # ---------------------------------------------------------------------------
 # overrelaxation
 # ---------------------------------------------------------------------------
