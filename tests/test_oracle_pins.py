@@ -15,8 +15,7 @@ import oracle
 from tests import stats_util
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(HERE)
-WORK = os.path.join(ROOT, "_work")
+BUILD = os.path.join(HERE, "_build")     # build output of the test's helper program
 
 
 # --------------------------------------------------------------------------
@@ -24,10 +23,10 @@ WORK = os.path.join(ROOT, "_work")
 # --------------------------------------------------------------------------
 def _torch_philox_ref():
     import torch.utils.cpp_extension as ce
-    exe = os.path.join(WORK, "ref_torch_philox")
+    exe = os.path.join(BUILD, "ref_torch_philox")
     src = os.path.join(HERE, "ref_torch_philox.cpp")
     if not os.path.exists(exe) or os.path.getmtime(exe) < os.path.getmtime(src):
-        os.makedirs(WORK, exist_ok=True)
+        os.makedirs(BUILD, exist_ok=True)
         subprocess.run(["g++", "-std=c++17", "-O1", "-I" + ce.include_paths()[0], "-o", exe, src],
                        check=True)
     return exe
