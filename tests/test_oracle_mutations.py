@@ -1,0 +1,74 @@
+"""Do the oracle's pins catch plausible mistakes?  Each case plants one
+mistake in a copy of the CPU oracle (on the CPU: a dropped dagger, swapped
+factors, a sign, a dropped factor, a wrong extent or constant), rebuilds it
+and runs the pin suite (tests/test_oracle_pins.py) against the copy, which
+must fail.
+
+Each case rebuilds the oracle copy and stops the pin suite at its first
+failure (~2 s a case).  One plausible mistake is known to pass every pin and
+is not listed: multiplying the sampled element on the other side of Vhat
+(Vhat^+ W instead of W Vhat^+) gives the same conditional law, since
+conjugation by Vhat preserves the Haar measure and the trace; that side is a
+convention of the random-number contract, fixed by the GPU-vs-oracle
+per-link parity tests instead.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+MUTATIONS = [
+    ("lower staple: dagger dropped", "or_qdag(link(U, xpm, nu), d);", "memcpy(d, link(U, xpm, nu), sizeof d);"),
+    ("upper staple: factors swapped", "or_qmul(link(U, xp, nu), d, t1);", "or_qmul(d, link(U, xp, nu), t1);"),
+    ("quaternion product: cross-product sign", "double r1 = a[0] * b[1] + b[0] * a[1] - (a[2] * b[3] - a[3] * b[2]);",
+     "double r1 = a[0] * b[1] + b[0] * a[1] + (a[2] * b[3] - a[3] * b[2]);"),
+    ("single precision: cos^2 -> cos", "(double)(c * c) * (double)l3", "(double)c * (double)l3"),
+    ("single precision: wrong Philox word", "*ub = or_u01_f32(r[2]);", "*ub = or_u01_f32(r[1]);"),
+    ("single precision: staple factors swapped", "qmul_f(a, b, t);\n        qmul_f(t, c, s);\n        for (int k = 0; k < 4; ++k)\n            V[k] += s[k];\n        int64_t xm",
+     "qmul_f(b, a, t);\n        qmul_f(t, c, s);\n        for (int k = 0; k < 4; ++k)\n            V[k] += s[k];\n        int64_t xm"),
+    ("Kennedy-Pendleton: cos^2 -> cos", "c * c * log(u3)", "c * log(u3)"),
+    ("Kennedy-Pendleton: accept test", "u4 * u4 <= 1.0 - lam2", "u4 <= 1.0 - lam2"),
+    ("Kennedy-Pendleton: x0 factor", "x0 = 1.0 - 2.0 * lam2;", "x0 = 1.0 - lam2;"),
+    ("Creutz: accept test", "if (u2 * u2 <= 1.0 - t * t) {", "if (u2 <= 1.0 - t * t) {"),
+    ("Creutz: exponent", "double e = exp(-2.0 * alpha);", "double e = exp(-alpha);"),
+    ("direction: cos(theta)", "double cth = 2.0 * u5 - 1.0;", "double cth = u5;"),
+    ("new link: no dagger on Vhat", "or_qdag(Vhat, Vd);", "memcpy(Vd, Vhat, sizeof Vd);"),
+    ("overrelaxation: dagger dropped", "or_qdag(Ul, Ud);", "memcpy(Ud, Ul, sizeof Ud);"),
+    ("plaquette: dagger dropped", "or_qdag(link(U, xnu, mu), c);", "memcpy(c, link(U, xnu, mu), sizeof c);"),
+    ("Polyakov loop: product order", "or_qmul(P, link(U, s + vs * t, 3), T);", "or_qmul(link(U, s + vs * t, 3), P, T);"),
+    ("Philox: Weyl constant", "k1 += 0xBB67AE85u;", "k1 += 0xBB67AE84u;"),
+    ("FP64 uniform: shift", "uint64_t m = w >> 12;", "uint64_t m = w >> 11;"),
+    ("hot start: Box-Muller angle", "r2 * sin(2.0 * OR_PI * u4)}", "r2 * sin(2.0 * OR_PI * u3)}"),
+    ("correlator: wrong extent", "int64_t sy = x + (int64_t)n[0] * ((y + r) % n[1] + (int64_t)n[1] * z);",
+     "int64_t sy = x + (int64_t)n[0] * ((y + r) % n[2] + (int64_t)n[1] * z);"),
+    ("beta convention", "double alpha = beta * k;", "double alpha = 0.5 * beta * k;"),
+    ("gauge transformation: dagger dropped", "or_qdag(g + 4 * j, gd);", "memcpy(gd, g + 4 * j, sizeof gd);"),
+]
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pins_catch_planted_mistake(name, old, new):
+    tree = os.path.join(HERE, "_build", "mutant")
+    if os.path.exists(tree):
+        shutil.rmtree(tree)
+    os.makedirs(tree)
+    ign = shutil.ignore_patterns("*.so", "__pycache__", "_build")
+    shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(tree, "oracle"), ignore=ign)
+    shutil.copytree(HERE, os.path.join(tree, "tests"), ignore=ign)
+    shutil.copy(os.path.join(ROOT, "pytest.ini"), tree)
+    src_path = os.path.join(tree, "oracle", "su2_oracle.c")
+    src = open(src_path).read()
+    # the first occurrence: the sampler steps of the heat bath come before
+    # their single-precision twin and the block move's neighbour redraw
+    assert old in src, "mutation anchor not found: " + name
+    open(src_path, "w").write(src.replace(old, new, 1))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join("tests", "test_oracle_pins.py")],
+                       cwd=tree, capture_output=True, text=True, timeout=900)
+    shutil.rmtree(tree)
+    assert r.returncode != 0, f"the pins did not catch: {name}\n{r.stdout[-2000:]}"
