@@ -11,12 +11,15 @@ Hastings step on the marginal of a block centre).
 - Stationary law: repeated moves of one class (nothing else moving) make
   each centre's link follow the marginal prod_o Z(beta|V_o(T)|); checked
   against a direct quadrature over SU(2).
+- The redraw of the integrated links: after a class of moves every
+  neighbour link follows its heat-bath conditional law given the rest
+  (probability-integral transform against the exact CDF).
 """
 import itertools
 
 import numpy as np
 import pytest
-from scipy import special
+from scipy import special, stats
 
 import oracle
 from tests import stats_util
@@ -153,3 +156,37 @@ def test_block_move_samples_the_marginal():
     for j in range(len(cen)):
         m, err, tau, _ = stats_util.gamma_method(np.array(series[j]))
         assert abs(m - ref[j]) <= 4 * err + 1e-3, (j, m, ref[j], err, tau)
+
+
+def test_block_move_redraws_the_neighbours_from_their_conditional_law():
+    # After a class of block moves each neighbour temporal link T(o) was drawn
+    # by heat bath given everything else, the centre after its decision
+    # included, and nothing in its staple moves later in the class (another
+    # centre of the class is >= 3 away from o, its neighbours >= 2, and the
+    # staple of a temporal link holds temporal links of its own slice at
+    # distance 1 only).  So F_alpha(w0) ~ U(0,1) with w0 = (1/2)Tr(T(o) Vhat_o),
+    # alpha = beta |V_o|.  A redraw at the wrong coupling, or none, fails.
+    n, beta, seed = (8, 8, 8, 4), 2.3, 17
+    U = oracle.init_hot(n, seed)
+    for s in range(10):
+        assert oracle.heatbath_sweep(n, U, beta, seed, s) == 0
+    rng = np.random.default_rng(3)
+    y = rng.normal(scale=0.3, size=(n[3], n[2], n[1], n[0], 6))
+    pit = []
+    for step in range(3):
+        for p, k in ((0, 0), (1, 3), (0, 5), (1, 6)):
+            f, _ = oracle.block_move(n, U, beta, seed, step, p, k, y)
+            assert f == 0
+            flat = U.reshape(-1, 4, 4)
+            for t, z, yy, x in itertools.product(range(n[3]), range(n[2]), range(n[1]), range(n[0])):
+                if (x + yy + z) % 2 != p or oracle.block_colour(x, yy, z) != k:
+                    continue
+                for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+                    o = _site(n, (x + dx) % n[0], (yy + dy) % n[1], (z + dz) % n[2], t)
+                    V = oracle.staple(n, U, o, 3)
+                    kv = np.linalg.norm(V)
+                    w0 = oracle.qmul(flat[o, 3], V / kv)[0]
+                    pit.append(float(stats_util.x0_cdf(np.array(beta * kv), np.array(w0))))
+    pit = np.array(pit)
+    assert pit.size >= 3000
+    assert stats.kstest(pit, "uniform").pvalue > 1e-4

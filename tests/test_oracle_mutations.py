@@ -1,11 +1,11 @@
 """Do the oracle's pins catch plausible mistakes?  Each case plants one
 mistake in a copy of the CPU oracle (on the CPU: a dropped dagger, swapped
 factors, a sign, a dropped factor, a wrong extent or constant), rebuilds it
-and runs the pin suite (tests/test_oracle_pins.py) against the copy, which
-must fail.
+and runs a pin (from tests/test_oracle_pins.py, or tests/test_oracle_block.py
+for the block move) against the copy, which must fail an assertion.
 
-Each case rebuilds the oracle copy and stops the pin suite at its first
-failure (~2 s a case).  One plausible mistake is known to pass every pin and
+Each case rebuilds the oracle copy and runs the pin named for it in
+CATCHES (a few seconds a case; the block move's stationary-law pin ~15 s).  One plausible mistake is known to pass every pin and
 is not listed: multiplying the sampled element on the other side of Vhat
 (Vhat^+ W instead of W Vhat^+) gives the same conditional law, since
 conjugation by Vhat preserves the Haar measure and the trace; that side is a
@@ -50,9 +50,59 @@ MUTATIONS = [
     ("gauge transformation: dagger dropped", "or_qdag(g + 4 * j, gd);", "memcpy(gd, g + 4 * j, sizeof gd);"),
 ]
 
+# Mistakes in the learned block move (Metropolis-Hastings on the block
+# marginal, then a heat-bath redraw of the integrated links), caught by its
+# own pins (tests/test_oracle_block.py).  A wrong proposal coefficient is not
+# among them: the move is exact for any proposal, so only its acceptance
+# changes.
+BLOCK_MUTATIONS = [
+    ("block move: proposal terms swapped", "half_tr(T, M) - half_tr(Tn, M);", "half_tr(Tn, M) - half_tr(T, M);"),
+    ("block move: marginal dropped", "double logr = block_log_marginal(beta, S, Tn) - block_log_marginal(beta, S, T) +",
+     "double logr = 0.0 +"),
+    ("block move: accept test reversed", "if (log(ua) < logr) {", "if (log(ua) > logr) {"),
+    ("block move: redraw at beta = 1", "double Vb[4] = {beta * V[0], beta * V[1], beta * V[2], beta * V[3]};",
+     "double Vb[4] = {V[0], V[1], V[2], V[3]};"),
+    ("block move: no redraw", "memcpy(U + (o * 4 + 3) * 4, Un, sizeof Un);", ";"),
+]
+
+# The pin that catches each mistake (others may catch it too).
+CATCHES = {
+    'lower staple: dagger dropped': 'test_staple_gives_local_action_change',
+    'upper staple: factors swapped': 'test_staple_gives_local_action_change',
+    'quaternion product: cross-product sign': 'test_quaternion_algebra_matches_matrices',
+    'single precision: cos^2 -> cos': 'test_single_precision_heatbath_law_and_agreement',
+    'single precision: wrong Philox word': 'test_single_precision_heatbath_law_and_agreement',
+    'single precision: staple factors swapped': 'test_single_precision_heatbath_law_and_agreement',
+    'Kennedy-Pendleton: cos^2 -> cos': 'test_single_link_sampler_law',
+    'Kennedy-Pendleton: accept test': 'test_single_link_sampler_law',
+    'Kennedy-Pendleton: x0 factor': 'test_single_link_sampler_law',
+    'Creutz: accept test': 'test_single_link_sampler_law',
+    'Creutz: exponent': 'test_single_link_sampler_law',
+    'direction: cos(theta)': 'test_single_link_sampler_law',
+    'new link: no dagger on Vhat': 'test_heatbath_pit_at_equilibrium',
+    'overrelaxation: dagger dropped': 'test_overrelaxation_invariants',
+    'plaquette: dagger dropped': 'test_plaquette_constant_field_closed_form',
+    'Polyakov loop: product order': 'test_gauge_invariance',
+    'Philox: Weyl constant': 'test_philox_matches_independent_engine',
+    'FP64 uniform: shift': 'test_u01_edges',
+    'hot start: Box-Muller angle': 'test_hot_start_is_haar',
+    'correlator: wrong extent': 'test_polyakov_closed_forms',
+    'beta convention': 'test_strong_coupling_plaquette',
+    'gauge transformation: dagger dropped': 'test_gauge_invariance',
+    'block move: proposal terms swapped': 'test_block_move_samples_the_marginal',
+    'block move: marginal dropped': 'test_block_move_samples_the_marginal',
+    'block move: accept test reversed': 'test_block_move_samples_the_marginal',
+    'block move: redraw at beta = 1': 'test_block_move_redraws_the_neighbours_from_their_conditional_law',
+    'block move: no redraw': 'test_block_move_redraws_the_neighbours_from_their_conditional_law',
+}
+
+CASES = ([m + ("test_oracle_pins.py",) for m in MUTATIONS]
+         + [m + ("test_oracle_block.py",) for m in BLOCK_MUTATIONS])
+
+
 @pytest.mark.slow
-@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_pins_catch_planted_mistake(name, old, new):
+@pytest.mark.parametrize("name,old,new,pins", CASES, ids=[c[0] for c in CASES])
+def test_pins_catch_planted_mistake(name, old, new, pins):
     tree = os.path.join(HERE, "_build", "mutant")
     if os.path.exists(tree):
         shutil.rmtree(tree)
@@ -67,8 +117,17 @@ def test_pins_catch_planted_mistake(name, old, new):
     # their single-precision twin and the block move's neighbour redraw
     assert old in src, "mutation anchor not found: " + name
     open(src_path, "w").write(src.replace(old, new, 1))
+    # the mutant must build: a failure to compile is not a caught mistake
+    b = subprocess.run([sys.executable, os.path.join("oracle", "build.py")], cwd=tree, capture_output=True,
+                       text=True, timeout=300)
+    assert b.returncode == 0, f"mutant does not build: {name}\n{b.stderr[-2000:]}"
+    # the copy's oracle and tests come first on the path; the statistics
+    # helpers the tests share with the package resolve to this repository
+    env = dict(os.environ, PYTHONPATH=ROOT)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join("tests", "test_oracle_pins.py")],
-                       cwd=tree, capture_output=True, text=True, timeout=900)
+                        os.path.join("tests", pins) + "::" + CATCHES[name]],
+                       cwd=tree, capture_output=True, text=True, timeout=900, env=env)
     shutil.rmtree(tree)
-    assert r.returncode != 0, f"the pins did not catch: {name}\n{r.stdout[-2000:]}"
+    summary = r.stdout.strip().splitlines()[-1] if r.stdout.strip() else ""
+    assert r.returncode == 1 and " failed" in summary and "error" not in summary, \
+        f"the pins did not catch: {name}\n{r.stdout[-2000:]}"
