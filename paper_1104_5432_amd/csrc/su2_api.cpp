@@ -158,7 +158,10 @@ WorkLayout work_layout(const int32_t n[4])
         uint64_t b = (items + 255) / 256;
         return (uint32_t)(b < cap ? (b > 0 ? b : 1) : cap);
     };
-    w.nblk_plaq = (uint32_t)((vol / 2 + 255) / 256); // one block per 256 cb indices
+    // one block per 256 cb indices: also the grid of an update class
+    // (class_blocks), whose blocks write here when a last sweep takes the
+    // plaquette, so the two must stay equal
+    w.nblk_plaq = (uint32_t)((vol / 2 + 255) / 256);
     w.nblk_poly = blocks(vs, 2048);
     w.nblk_corr = blocks(vs, 1024);
     uint64_t off = 256; // flags word
