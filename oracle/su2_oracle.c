@@ -17,6 +17,9 @@
  *  - heat bath: conditional law of one link (KS against the exact density,
  *    mean against a ratio of Bessel functions), probability-integral
  *    transform at equilibrium, strong- and weak-coupling limits;
+ *  - heat bath with single-precision links: the same exact law (KS) and
+ *    agreement with the double-precision step except where a decision
+ *    flips between 23-bit and 52-bit arithmetic;
  *  - overrelaxation: action conservation and involution;
  *  - observables: cold start = 1, gauge invariance, Z2 centre symmetry.
  */
