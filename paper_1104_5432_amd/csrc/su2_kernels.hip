@@ -7,6 +7,7 @@
 #include "su2_launch.hpp"
 
 #include <cstring>
+#include <type_traits>
 
 namespace su2 {
 
@@ -285,13 +286,20 @@ __device__ __forceinline__ Quat<T> overrelax_link(const Links<T> &U, const A &ad
                                                   PlaneTerms<T> *terms)
 {
     // The link being replaced is read by this update only (non-temporal).
-    // Its load is issued before the staple's loads: left to the scheduler it
-    // is sunk to its use after the staple algebra, which exposes a second
-    // memory round trip per wave (64^4 FP32 class: 218.5 -> 216.0 us).
+    // FP32: its load is issued before the staple's loads; left to the
+    // scheduler it is sunk to its use after the staple algebra, which
+    // exposes a second memory round trip per wave (64^4 class: 218.5 ->
+    // 216.0 us).  FP64 keeps the sunk load: issued first, the FP64 class
+    // took 4.5% longer (485 -> 507 us) and fetched 6% more bytes beyond L2.
     const uint32_t own = ad.at(0, 0, 0, 0);
-    const Quat<T> u = ad.ld_nt(U, MU, par, own);
-    __builtin_amdgcn_sched_barrier(0);
+    Quat<T> u;
+    if constexpr (std::is_same<T, float>::value) {
+        u = ad.ld_nt(U, MU, par, own);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     const Quat<T> V = staple_impl<T, MU, PLAQ>(U, ad, par, terms);
+    if constexpr (!std::is_same<T, float>::value)
+        u = ad.ld_nt(U, MU, par, own);
     const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
     const T k = sqrt(k2);
     if (!isfinite(k)) {
