@@ -139,7 +139,9 @@ def scan(args):
     32^3x4, 48^3x6, 64^3x8, beta_j = 2.2 + 0.5 j/15, lattice_id j, one
     captured graph per sweep (batched heat bath reading the sweep index from
     device memory, args.or_per_hb batched overrelaxation sweeps, Polyakov
-    loop and correlator of all lattices in three launches, sweep advance)."""
+    loop and correlator of all lattices in three launches, sweep advance).
+    After the timed region the per-sweep correlators give each lattice's
+    string tension (host analysis)."""
     import torch
     import paper_1104_5432_amd as su2
 
@@ -165,9 +167,12 @@ def scan(args):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
+    chist = torch.zeros((args.steps + args.warmup,) + tuple(corr.shape), dtype=torch.float64, device="cuda:0")
+
     def sweep(k):
         graph.replay()
         hist[k].copy_(poly, non_blocking=True)
+        chist[k].copy_(corr, non_blocking=True)
 
     for k in range(args.warmup):
         sweep(k)
@@ -186,6 +191,7 @@ def scan(args):
     for lat in lats:
         flags |= int(su2.su2_get_flags(lat).item())
     absl = hist[args.warmup:, :, 0].abs().mean(0).cpu().tolist()
+    sigma = scan_string_tension(lats, betas, chist[args.warmup:].cpu().numpy())
     rec = {
         "metric": METRIC,
         "value": updates * args.steps / (ms * 1e-3),
@@ -209,9 +215,38 @@ def scan(args):
             "link_updates_per_step": updates,
         },
         "polyakov_abs_mean_by_beta": dict(zip([round(b, 4) for b in betas], absl)),
+        "string_tension_by_beta": sigma,
         "check": {"flags": flags},
     }
     print(json.dumps(rec), flush=True)
+
+
+def scan_string_tension(lats, betas, corr_hist, n_blocks=20):
+    """Host analysis of the scan's per-sweep correlators (eqs. (2)-(3) and
+    the fit that follows them): for each lattice, a F(r) = -ln C(r)/Nt - ln 4/Nt
+    fitted with a0 - a1/r + sigma r over r = 1..rmax, rmax the largest
+    separation up to which every mean C(r) exceeds three of its standard
+    errors (at least four points, else no fit); jackknife errors over blocks
+    of consecutive sweeps (blocks shorter than the autocorrelation time make
+    them optimistic)."""
+    import numpy as np
+    from paper_1104_5432_amd import analysis
+    out = {}
+    for j, (lat, beta) in enumerate(zip(lats, betas)):
+        R = min(lat.n[:3]) // 2
+        c = corr_hist[:, j, :R]
+        if c.shape[0] < 2 * n_blocks:
+            continue
+        mean = c.mean(0)
+        err = c.std(0, ddof=1) / np.sqrt(c.shape[0])
+        ok = mean > 3 * err
+        rmax = int(np.argmin(ok)) if not ok.all() else R
+        if rmax < 4:
+            out[round(beta, 4)] = {"nt": lat.n[3], "sigma": None, "rmax": rmax}
+            continue
+        p, perr, _ = analysis.string_tension(c, lat.n[3], rmin=1, rmax=rmax, n_blocks=n_blocks)
+        out[round(beta, 4)] = {"nt": lat.n[3], "sigma": float(p[2]), "sigma_err": float(perr[2]), "rmax": rmax}
+    return out
 
 
 def learned_workload(args):
