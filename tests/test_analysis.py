@@ -117,3 +117,24 @@ def test_sigma_of_t_ansatz_fits_recover_the_papers_parameters(ansatz):
     assert np.allclose(p, truth, rtol=1e-6, atol=1e-6) and chi2 < 1e-6
     # sqrt ansatz: sigma(Tc) = a sqrt(1 - b) ~ 0 for b ~ 1; critical: sigma(Tc) = 0
     assert f(np.array([1.0]), *truth)[0] < 0.03
+
+
+def test_scan_string_tension_recovers_a_known_potential():
+    # the benchmark's host analysis of per-sweep correlators: a confined
+    # lattice (linear potential) gives its sigma back within errors, and a
+    # deconfined one (C(r) flat at |L|^2) gives sigma ~ 0
+    import types
+    import bench
+    rng = np.random.default_rng(9)
+    lats = [types.SimpleNamespace(n=(16, 16, 16, 4)), types.SimpleNamespace(n=(16, 16, 16, 4))]
+    r = np.arange(1.0, 9.0)
+    aF = 0.4 - 0.25 / r + 0.12 * r
+    C_conf = np.exp(-aF * 4 - np.log(4.0))
+    C_deconf = np.full_like(r, 0.09)
+    hist = np.empty((800, 2, 8))
+    hist[:, 0] = C_conf * (1 + 0.02 * rng.normal(size=(800, 8)))
+    hist[:, 1] = C_deconf * (1 + 0.02 * rng.normal(size=(800, 8)))
+    out = bench.scan_string_tension(lats, [2.2, 2.6], hist)
+    conf, deconf = out[2.2], out[2.6]
+    assert conf["rmax"] >= 4 and abs(conf["sigma"] - 0.12) < 4 * conf["sigma_err"] + 1e-3
+    assert abs(deconf["sigma"]) < 4 * deconf["sigma_err"] + 1e-3
