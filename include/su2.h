@@ -152,16 +152,20 @@ int su2_polyakov(const su2_lattice_t *lat, double *d_out, double *d_corr, void *
  * the plaquettes of planes (nu, mu), nu < mu, is final, and each such
  * plaquette holds exactly one odd mu-link, so the classes (1,odd), (2,odd),
  * (3,odd) take the half traces of their new links with the staple products
- * they already formed (FP64 from the half trace on).  The links are
- * bitwise those of su2_heatbath_sweep; the plaquette agrees with
- * su2_plaquette to the summation order (FP64) or to the rounding of FP32
- * products (FP32). */
+ * they already formed (FP64 from the half trace on; in FP32 the two
+ * plaquettes of one plane through a link share one half trace of the summed
+ * staple products).  The links are bitwise those of su2_heatbath_sweep; the
+ * plaquette agrees with su2_plaquette to the summation order (FP64) or to
+ * the rounding of FP32 products (FP32).  Uses the plaquette partials of the
+ * lattice's workspace.  Errors: as su2_heatbath_sweep, plus SU2_EINVAL for a
+ * NULL d_plaq and SU2_EALIGN for one not 8-byte aligned. */
 int su2_heatbath_sweep_measured(const su2_lattice_t *lat, double beta, uint64_t seed, uint32_t sweep,
                                 double *d_plaq, void *stream);
 
 /* su2_overrelax with the mean plaquette of the final configuration left in
  * d_plaq, measured by the last sweep as in su2_heatbath_sweep_measured
- * (n_sweeps = 0: su2_plaquette of the current configuration). */
+ * (n_sweeps = 0: su2_plaquette of the current configuration).  Errors: as
+ * su2_overrelax, plus those of d_plaq as in su2_heatbath_sweep_measured. */
 int su2_overrelax_measured(const su2_lattice_t *lat, int32_t n_sweeps, double *d_plaq, void *stream);
 
 /* Both measurements of a configuration in one pass over the links (Sec. 2.1
@@ -211,7 +215,10 @@ int su2_batch_overrelax(const su2_lattice_t *lats, int32_t count, const void *d_
  * r = 1..min(Nx,Ny,Nz)/2 of lattice j, and its entries beyond are left
  * untouched; corr_stride must be >= the largest min(Nx,Ny,Nz)/2 of the
  * batch.  Uses each lattice's workspace; lats and d_table as for the other
- * batched calls (the table of su2_batch_fill for these descriptors). */
+ * batched calls (the table of su2_batch_fill for these descriptors).
+ * Errors: those of the descriptors as in su2_batch_fill; SU2_EINVAL for a
+ * NULL or misaligned d_table, a NULL d_poly or a corr_stride too small;
+ * SU2_EALIGN for d_poly or d_corr not 8-byte aligned. */
 int su2_batch_polyakov(const su2_lattice_t *lats, int32_t count, const void *d_table, double *d_poly,
                        double *d_corr, int32_t corr_stride, void *stream);
 
