@@ -683,6 +683,54 @@ __device__ __forceinline__ Quat<T> staple_impl(const Links<T> &U, const A &ad, i
     return V;
 }
 
+// The staple in two steps: load its 18 links, then form it.  Used where
+// independent work (the heat bath's random numbers) is placed between the
+// two, while the loads are in flight.  Same products and sums, in the same
+// order, as staple_impl.
+template <class T, int MU, class A>
+__device__ __forceinline__ void staple_load(const Links<T> &U, const A &ad, int par, Quat<T> (&L)[4][6])
+{
+    const int opp = par ^ 1;
+    const int32_t m0 = (MU == 0), m1 = (MU == 1), m2 = (MU == 2), m3 = (MU == 3);
+    const uint32_t i_xp = ad.at(m0, m1, m2, m3);
+    const uint32_t i_x = ad.at(0, 0, 0, 0);
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU)
+            continue;
+        const int32_t e0 = (nu == 0), e1 = (nu == 1), e2 = (nu == 2), e3 = (nu == 3);
+        const uint32_t i_xpn = ad.at(e0, e1, e2, e3);
+        const uint32_t i_xmn = ad.at(-e0, -e1, -e2, -e3);
+        const uint32_t i_xpmn = ad.at(m0 - e0, m1 - e1, m2 - e2, m3 - e3);
+        L[nu][0] = ad.ld(U, nu, opp, i_xp);
+        L[nu][1] = ad.ld(U, MU, opp, i_xpn);
+        L[nu][2] = ad.ld(U, nu, par, i_x);
+        L[nu][3] = ad.ld(U, nu, par, i_xpmn);
+        L[nu][4] = ad.ld(U, MU, opp, i_xmn);
+        L[nu][5] = ad.ld(U, nu, opp, i_xmn);
+    }
+}
+
+template <class T, int MU, bool TERMS>
+__device__ __forceinline__ Quat<T> staple_compute(const Quat<T> (&L)[4][6], PlaneTerms<T> *terms)
+{
+    Quat<T> V = {0, 0, 0, 0};
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU)
+            continue;
+        const Quat<T> su = qmul_nd(qmul_nd(L[nu][0], L[nu][1]), L[nu][2]);
+        qacc(V, su);
+        const Quat<T> sl = qmul(qmul_dd(L[nu][3], L[nu][4]), L[nu][5]);
+        qacc(V, sl);
+        if constexpr (TERMS) {
+            if (nu < MU)
+                terms->s[nu] = {su.w + sl.w, su.x + sl.x, su.y + sl.y, su.z + sl.z};
+        }
+    }
+    return V;
+}
+
 template <class T, int MU, class A>
 __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const A &ad, int par)
 {

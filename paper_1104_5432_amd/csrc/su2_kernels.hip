@@ -29,15 +29,15 @@ namespace su2 {
 template <class T>
 struct KP;
 
+// One attempt from its two Philox outputs: ra = counter 4a, rb = 4a + 1.
 template <>
 struct KP<double> {
-    __device__ static __forceinline__ bool attempt(double inv2a, uint32_t site, uint32_t c1, uint32_t sweep,
-                                                   uint32_t a, uint32_t k0, uint32_t k1, double &x0,
+    __device__ static __forceinline__ bool attempt(double inv2a, const U32x4 &ra, const U32x4 &rb, double &x0,
                                                    double &xlen)
     {
         double u1, u2, u3, u4;
-        Draw<double>::two(philox(site, c1, sweep, 4u * a, k0, k1), u1, u2);
-        Draw<double>::two(philox(site, c1, sweep, 4u * a + 1u, k0, k1), u3, u4);
+        Draw<double>::two(ra, u1, u2);
+        Draw<double>::two(rb, u3, u4);
         const double c = cos((2.0 * kPi) * u2);
         const double lam2 = -(log(u1) + c * c * log(u3)) * inv2a;
         if (lam2 <= 1.0 && u4 * u4 <= 1.0 - lam2) {
@@ -51,12 +51,9 @@ struct KP<double> {
 
 template <>
 struct KP<float> {
-    __device__ static __forceinline__ bool attempt(double inv2a, uint32_t site, uint32_t c1, uint32_t sweep,
-                                                   uint32_t a, uint32_t k0, uint32_t k1, double &x0,
+    __device__ static __forceinline__ bool attempt(double inv2a, const U32x4 &ra, const U32x4 &rb, double &x0,
                                                    double &xlen)
     {
-        const U32x4 ra = philox(site, c1, sweep, 4u * a, k0, k1);
-        const U32x4 rb = philox(site, c1, sweep, 4u * a + 1u, k0, k1);
         const float u1 = u01_f32(ra.r0), u2 = u01_f32(ra.r2);
         const float u3 = u01_f32(rb.r0), u4 = u01_f32(rb.r2);
         const float c = cospif(2.0f * u2);
@@ -71,12 +68,12 @@ struct KP<float> {
     }
 };
 
+// One Creutz attempt from its Philox output ra (counter 4a).
 template <class T>
-__device__ __forceinline__ bool creutz_attempt(double alpha, uint32_t site, uint32_t c1, uint32_t sweep,
-                                               uint32_t a, uint32_t k0, uint32_t k1, double &x0, double &xlen)
+__device__ __forceinline__ bool creutz_attempt(double alpha, const U32x4 &ra, double &x0, double &xlen)
 {
     double u1, u2;
-    Draw<T>::two(philox(site, c1, sweep, 4u * a, k0, k1), u1, u2);
+    Draw<T>::two(ra, u1, u2);
     double t;
     if (alpha < 1e-8) {
         t = 2.0 * u1 - 1.0;
@@ -92,14 +89,26 @@ __device__ __forceinline__ bool creutz_attempt(double alpha, uint32_t site, uint
     return false;
 }
 
+// An attempt from its random words (ra, rb as above; Creutz uses ra only).
+template <class T>
+__device__ __forceinline__ bool sampler_attempt_drawn(double alpha, double inv2a, const U32x4 &ra, const U32x4 &rb,
+                                                      double &x0, double &xlen)
+{
+    if (alpha >= 2.0)
+        return KP<T>::attempt(inv2a, ra, rb, x0, xlen);
+    return creutz_attempt<T>(alpha, ra, x0, xlen);
+}
+
+// Attempt a of the link at `site`, drawing its words.
 template <class T>
 __device__ __forceinline__ bool sampler_attempt(double alpha, double inv2a, uint32_t site, uint32_t c1,
                                                 uint32_t sweep, uint32_t a, uint32_t k0, uint32_t k1, double &x0,
                                                 double &xlen)
 {
+    const U32x4 ra = philox(site, c1, sweep, 4u * a, k0, k1);
     if (alpha >= 2.0)
-        return KP<T>::attempt(inv2a, site, c1, sweep, a, k0, k1, x0, xlen);
-    return creutz_attempt<T>(alpha, site, c1, sweep, a, k0, k1, x0, xlen);
+        return KP<T>::attempt(inv2a, ra, philox(site, c1, sweep, 4u * a + 1u, k0, k1), x0, xlen);
+    return creutz_attempt<T>(alpha, ra, x0, xlen);
 }
 
 // Direction of the vector part: cos(theta) = 2 u5 - 1, phi = 2 pi u6.
@@ -185,13 +194,34 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     double alpha = 0.0;
     bool need = false;
     PlaneTerms<T> terms;
+    // Random words of attempt 0 (counters 0, 1) and of the direction
+    // (counter 2): they do not depend on the staple, so for FP32 links with
+    // column addressing they are drawn between issuing the staple's loads
+    // and using them, while the loads are in flight (64^4 class: 213.5 ->
+    // 208.7 us).  FP64 keeps the staple's interleaved loads and draws in the
+    // order they are used: holding all 18 links would take 179 VGPRs and
+    // halve its occupancy.
+    U32x4 r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, rdir = {0, 0, 0, 0};
     if (valid) {
         Quat<T> V;
         if constexpr (COL) {
             const ColAddr ad = col_addr(g, i, par);
             own = ad.at(0, 0, 0, 0);
             site = ad.site();
-            V = staple_impl<T, MU, PLAQ>(U, ad, par, &terms);
+            if constexpr (std::is_same<T, float>::value) {
+                Quat<T> L[4][6];
+                staple_load<T, MU>(U, ad, par, L);
+                __builtin_amdgcn_sched_barrier(0);
+                r0 = philox(site, c1, sweep, 0u, k0, k1);
+                r1 = philox(site, c1, sweep, 1u, k0, k1);
+                rdir = philox(site, c1, sweep, 2u, k0, k1);
+                __builtin_amdgcn_sched_barrier(0);
+                V = staple_compute<T, MU, PLAQ>(L, &terms);
+            } else {
+                V = staple_impl<T, MU, PLAQ>(U, ad, par, &terms);
+                r0 = philox(site, c1, sweep, 0u, k0, k1);
+                r1 = philox(site, c1, sweep, 1u, k0, k1);
+            }
         } else {
             own = walk_cb(i, g.ord);
             CbAddr ad;
@@ -200,6 +230,8 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
             ad.g = &g;
             site = ad.s.site;
             V = staple_impl<T, MU, PLAQ>(U, ad, par, &terms);
+            r0 = philox(site, c1, sweep, 0u, k0, k1);
+            r1 = philox(site, c1, sweep, 1u, k0, k1);
         }
         const T k = sqrt(V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z);
         if (!isfinite(k)) {
@@ -219,7 +251,7 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     double x0 = 0.0, xlen = 0.0;
     bool ok = false;
     if (need)
-        ok = sampler_attempt<T>(alpha, inv2a, site, c1, sweep, 0u, k0, k1, x0, xlen);
+        ok = sampler_attempt_drawn<T>(alpha, inv2a, r0, r1, x0, xlen);
     const bool retry = need && !ok;
 
     // compact the rejected lanes of the block
@@ -264,7 +296,9 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     }
     Quat<T> Un = {1, 0, 0, 0};
     if (ok) {
-        const Quat<T> X = Direction<T>::make(x0, xlen, philox(site, c1, sweep, 2u, k0, k1));
+        if constexpr (!(COL && std::is_same<T, float>::value))
+            rdir = philox(site, c1, sweep, 2u, k0, k1);
+        const Quat<T> X = Direction<T>::make(x0, xlen, rdir);
         Un = unitize(qmul_nd(X, Vh));
         if constexpr (COL)
             U.stb(MU, par, own, Un);
