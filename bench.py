@@ -53,10 +53,13 @@ def parse():
                          "--no-autotune uses --tile/--tile-y)")
     ap.add_argument("--train", type=int, default=10000,
                     help="learned workload: heat-bath configurations to train on")
-    ap.add_argument("--workload", choices=["single", "scan", "learned", "precision"], default="single",
+    ap.add_argument("--workload", choices=["single", "scan", "learned", "precision", "paper"], default="single",
                     help="single: one lattice (--shape); scan: 16 lattices mixing 32^3x4, 48^3x6, "
                          "64^3x8 at beta 2.2..2.7, one captured graph replay per sweep; learned: the "
-                         "learned block proposal at 16^3x4; precision: FP32 against FP64 observables")
+                         "learned block proposal at 16^3x4; precision: FP32 against FP64 observables; "
+                         "paper: the paper's own benchmark (random start, 100 heat-bath iterations at "
+                         "beta 6.0 with the mean plaquette each) over lattice sizes, FP32 and FP64, "
+                         "against one core of the CPU oracle")
     ap.add_argument("--fused-plaquette", action=argparse.BooleanOptionalAction, default=True,
                     help="take the plaquette in the last sweep of the step (no separate pass); "
                          "--no-fused-plaquette measures it with the one-pass measurement kernel")
@@ -317,6 +320,116 @@ def learned_workload(args):
     print(json.dumps(rec), flush=True)
 
 
+def oracle_one_core_rate(n, beta, seed, sweeps):
+    """Link updates/s of the FP64 oracle on one host core (heat-bath sweeps
+    with the plaquette after each), run in a child process whose OpenMP
+    runtime is limited to one thread."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r); import oracle\n"
+            "n = %r\nU = oracle.init_hot(n, %d)\nt = time.perf_counter()\n"
+            "for s in range(%d):\n    oracle.heatbath_sweep(n, U, %r, %d, s); oracle.plaquette(n, U)\n"
+            "dt = time.perf_counter() - t\nprint(oracle.num_threads(), dt)\n") % (ROOT, tuple(n), seed, sweeps, beta,
+                                                                                seed)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    threads, dt = out.stdout.split()
+    vol = n[0] * n[1] * n[2] * n[3]
+    return 4 * vol * sweeps / float(dt), int(threads), float(dt)
+
+
+def paper_workload(args):
+    """The paper's own benchmark (Sec. 2.1): a random SU(2) start, then 100
+    heat-bath iterations at beta = 6.0 with the mean plaquette computed at
+    each, for several lattice sizes, in single and double precision, and
+    the speed-up over one CPU core.  Here the plaquette is taken by each
+    sweep's last classes (su2_heatbath_sweep_measured, a device array per
+    iteration); each size is timed as a host loop of calls and as one
+    captured graph of the 100 iterations (whose plaquettes must equal the
+    loop's bitwise).  The CPU side is the FP64 oracle on one host core,
+    timed on 20 iterations of a 16^4 lattice (its rate per link update does
+    not depend on the size)."""
+    import torch
+    import paper_1104_5432_amd as su2
+    from paper_1104_5432_amd import autotune
+
+    beta, iters = 6.0, 100
+    sizes = (8, 16, 24, 32, 48, 64)
+    dev = torch.device("cuda:0")
+    rows = []
+    for prec in ("f32", "f64"):
+        for L in sizes:
+            n = (L, L, L, L)
+            tile, tile_y = autotune.tune(n, prec, device=dev) if args.autotune else (0, 0)
+            lat = su2.Lattice(n, prec, device=dev, tile=tile, tile_y=tile_y)
+            plaq = torch.empty((iters, 7), dtype=torch.float64, device=dev)
+            su2.su2_init_hot(lat, args.seed)
+            for s in range(3):                                   # untimed warm-up
+                su2.su2_heatbath_sweep(lat, beta, args.seed, s)
+            su2.su2_init_hot(lat, args.seed)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for s in range(iters):
+                su2.su2_heatbath_sweep_measured(lat, beta, args.seed, s, plaq[s])
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            # the same 100 iterations captured once in a graph and replayed from
+            # the same start: the launches of small lattices stop waiting on the
+            # host loop, and the plaquettes must come out bitwise the same
+            eager = plaq.clone()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                for s in range(iters):
+                    su2.su2_heatbath_sweep_measured(lat, beta, args.seed, s, plaq[s])
+            su2.su2_init_hot(lat, args.seed)
+            graph.replay()                                       # untimed: first replay uploads
+            su2.su2_init_hot(lat, args.seed)
+            torch.cuda.synchronize()
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms_graph = e0.elapsed_time(e1)
+            if not torch.equal(plaq, eager):
+                raise RuntimeError(f"graph replay differs from the eager loop at {n} {prec}")
+            vol = L ** 4
+            rows.append({"lattice": list(n), "prec": prec, "ms_100_iterations": ms,
+                         "link_updates_per_s": 4 * vol * iters / (ms * 1e-3),
+                         "ms_100_iterations_graph": ms_graph,
+                         "link_updates_per_s_graph": 4 * vol * iters / (ms_graph * 1e-3),
+                         "plaquette_last": float(plaq[iters - 1, 0].item()), "walk": [tile, tile_y]})
+            del lat, plaq, graph
+            torch.cuda.empty_cache()
+    cpu_rate, cpu_threads, cpu_s = oracle_one_core_rate((16, 16, 16, 16), beta, args.seed, 20)
+    for r in rows:
+        r["speedup_vs_one_core"] = r["link_updates_per_s"] / cpu_rate
+        r["speedup_vs_one_core_graph"] = r["link_updates_per_s_graph"] / cpu_rate
+    head = next(r for r in rows if r["prec"] == "f32" and r["lattice"][0] == 64)
+    rec = {
+        "metric": METRIC,
+        "value": head["link_updates_per_s"],
+        "unit": "link updates/s",
+        "n_gpus": 1,
+        "steps": iters,
+        "warmup": 3,
+        "ms_per_step": head["ms_100_iterations"] / iters,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "the paper's benchmark: random SU(2) start, 100 heat-bath iterations at beta 6.0 with "
+                        "the mean plaquette each, lattices 8^4..64^4, FP32 and FP64; value: 64^4 FP32",
+        },
+        "by_size": rows,
+        "cpu_one_core": {"value": cpu_rate, "unit": "link updates/s", "cores": cpu_threads, "kind": "oracle",
+                         "sample": f"16^4 FP64 oracle, 20 heat-bath iterations with the plaquette, {cpu_s:.1f} s"},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def precision_workload(args):
     """FP32 against FP64 links on the benchmarked lattice: for beta 2.3, 2.5
     and 6.0 an FP64 and an FP32 chain (hot start, args.steps steps of 1 heat
@@ -396,6 +509,9 @@ def main():
         return
     if args.workload == "precision":
         precision_workload(args)
+        return
+    if args.workload == "paper":
+        paper_workload(args)
         return
 
     import torch

@@ -21,8 +21,15 @@ def test_more_than_one_gpu_exits_with_a_message():
 def test_help_lists_the_workloads():
     r = _run("--help")
     assert r.returncode == 0
-    for w in ("single", "scan", "learned", "precision", "--autotune", "--tile-y", "--fused-plaquette"):
+    for w in ("single", "scan", "learned", "precision", "paper", "--autotune", "--tile-y", "--fused-plaquette"):
         assert w in r.stdout
+
+
+def test_one_core_oracle_rate_runs_single_threaded():
+    sys.path.insert(0, ROOT)
+    import bench
+    rate, threads, seconds = bench.oracle_one_core_rate((4, 4, 4, 4), 6.0, 1234, 1)
+    assert threads == 1 and rate > 0 and seconds > 0
 
 
 def test_stored_traffic_lookup_matches_walk_and_sources(tmp_path, monkeypatch):
