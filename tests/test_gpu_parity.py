@@ -275,6 +275,38 @@ def test_fp32_heatbath_chain_matches_single_precision_oracle(su2, beta):
     assert np.median(d) <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_paper_benchmark_iterations_match_oracle(su2, prec):
+    # the paper's benchmark (Sec. 2.1) at a small size: from the random
+    # start, heat-bath iterations at beta = 6.0 with the mean plaquette of
+    # each, every iteration's plaquette against the oracle's chain (FP32:
+    # the oracle's single-precision step, plaquette in FP64 of its links)
+    n, seed, beta, iters = (8, 8, 8, 8), 2011, 6.0, 4
+    lat = _lat(su2, n, prec)
+    su2.su2_init_hot(lat, seed)
+    _sync()
+    ref = su2.to_canonical(lat).numpy()
+    plaq = torch.empty((iters, 7), dtype=torch.float64, device="cuda")
+    for s in range(iters):
+        su2.su2_heatbath_sweep_measured(lat, beta, seed, s, plaq[s])
+    _sync()
+    got = plaq.cpu().numpy()
+    tol = 1e-12 if prec == "f64" else 2e-6
+    for s in range(iters):
+        if prec == "f64":
+            oracle.heatbath_sweep(n, ref, beta, seed, s)
+        else:
+            for mu in range(4):
+                for par in range(2):
+                    assert oracle.heatbath_halfsweep_f32(n, ref, beta, seed, s, mu, par) == 0
+        p, planes = oracle.plaquette(n, ref)
+        assert abs(got[s, 0] - p) <= tol and np.max(np.abs(got[s, 1:] - planes)) <= tol, s
+    # from the random start (plaquette ~0) the plaquette climbs every
+    # iteration towards its weak-coupling value ~1 - 3/(4 beta)
+    assert np.all(np.diff(got[:, 0]) > 0) and got[-1, 0] < 1 - 3 / (4 * beta)
+    assert _flags(su2, lat) == 0
+
+
 # ---------------------------------------------------------------------------
 # overrelaxation
 # ---------------------------------------------------------------------------
