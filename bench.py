@@ -499,7 +499,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the lattice update is single-GPU in this build)", file=sys.stderr)
+              "(one lattice is updated on one GPU; sharding is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "scan":
         scan(args)

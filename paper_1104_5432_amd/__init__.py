@@ -90,7 +90,7 @@ _SIGNATURES = {
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+            f"{LIB_PATH} is not built; run `python paper_1104_5432_amd/build.py` "
             "(hipcc for gfx950). There is no CPU fallback.")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGNATURES.items():
