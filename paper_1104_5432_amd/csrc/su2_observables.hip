@@ -316,6 +316,62 @@ __global__ void plaq_total_kernel(double *out)
         out[0] = (out[1] + out[2] + out[3] + out[4] + out[5] + out[6]) / 6.0;
 }
 
+// colsum_kernel over the six planes and plaq_total_kernel in one block: each
+// thread adds its partials of a plane in the same order as colsum_body, the
+// block sum and the final mean are the same expressions, so the results are
+// bitwise those of the two launches.  Used for short columns, where the
+// second launch costs more than one block reading all six.
+__global__ __launch_bounds__(kBlock) void plaq_finish_kernel(const double *partials, uint32_t nblk, double scale,
+                                                             double *out)
+{
+    __shared__ double lds[kBlock / 64][6];
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    uint32_t b = threadIdx.x;
+    for (; b + 7u * kBlock < nblk; b += 8u * kBlock) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const double *col = partials + (size_t)j * nblk;
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] = col[b + (uint32_t)u * kBlock];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                acc[j] += v[u];
+        }
+    }
+    for (; b < nblk; b += kBlock)
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            acc[j] += partials[(size_t)j * nblk + b];
+    block_sum<6>(acc, lds);
+    if (threadIdx.x == 0) {
+        // the two-launch path rounds each scaled plane before the mean
+#pragma clang fp contract(off)
+        double p[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            p[j] = acc[j] * scale;
+            out[1 + j] = p[j];
+        }
+        out[0] = (p[0] + p[1] + p[2] + p[3] + p[4] + p[5]) / 6.0;
+    }
+}
+
+// Columns up to this many partials are finished by plaq_finish_kernel.
+constexpr uint32_t kFinishOneBlock = 2048;
+
+static void launch_plaquette_finish(const double *partials, uint32_t nblk, double scale, double *d_out,
+                                    hipStream_t st)
+{
+    if (nblk <= kFinishOneBlock) {
+        plaq_finish_kernel<<<1, kBlock, 0, st>>>(partials, nblk, scale, d_out);
+    } else {
+        colsum_kernel<<<6, kBlock, 0, st>>>(partials, nblk, scale, d_out + 1);
+        plaq_total_kernel<<<1, 64, 0, st>>>(d_out);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
@@ -324,8 +380,7 @@ __global__ void plaq_total_kernel(double *out)
 void launch_plaquette_sum(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
 {
     double *partials = reinterpret_cast<double *>(a.work + w.off_plaq);
-    colsum_kernel<<<6, kBlock, 0, st>>>(partials, w.nblk_plaq, 1.0 / (double)a.volume, d_out + 1);
-    plaq_total_kernel<<<1, 64, 0, st>>>(d_out);
+    launch_plaquette_finish(partials, w.nblk_plaq, 1.0 / (double)a.volume, d_out, st);
 }
 
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
@@ -346,8 +401,7 @@ void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, h
         else
             plaquette_kernel<double, false><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
     }
-    colsum_kernel<<<6, kBlock, 0, st>>>(partials, w.nblk_plaq, 1.0 / (double)a.volume, d_out + 1);
-    plaq_total_kernel<<<1, 64, 0, st>>>(d_out);
+    launch_plaquette_finish(partials, w.nblk_plaq, 1.0 / (double)a.volume, d_out, st);
 }
 
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st)
