@@ -445,8 +445,7 @@ void launch_measure(const LaunchArgs &a, const WorkLayout &w, double *d_plaq, do
         measure_kernel<float><<<w.nblk_meas, kBlock, 0, st>>>(links_of<float>(a), g, Lf, pm);
     else
         measure_kernel<double><<<w.nblk_meas, kBlock, 0, st>>>(links_of<double>(a), g, Lf, pm);
-    colsum_kernel<<<6, kBlock, 0, st>>>(pm, w.nblk_meas, 1.0 / (double)a.volume, d_plaq + 1);
-    plaq_total_kernel<<<1, 64, 0, st>>>(d_plaq);
+    launch_plaquette_finish(pm, w.nblk_meas, 1.0 / (double)a.volume, d_plaq, st);
     colsum_kernel<<<2, kBlock, 0, st>>>(pm + (size_t)6 * w.nblk_meas, w.nblk_meas, 1.0 / (double)g.vs, d_poly);
     if (d_corr && w.rmax > 0) {
         double *cp = reinterpret_cast<double *>(a.work + w.off_corr);
