@@ -409,7 +409,6 @@ static uint32_t heatbath_link_f32(double Ulink[4], const float V[4], double beta
             Vhat[j] = V[j] * inv;
     }
     double alpha = beta * (double)k;
-    double inv2a = 1.0 / (2.0 * (alpha > 1.0 ? alpha : 1.0));
 
     double x0 = 0.0, xlen = 0.0;
     int accepted = 0;
@@ -420,7 +419,9 @@ static uint32_t heatbath_link_f32(double Ulink[4], const float V[4], double beta
             draw_f32(seed, site, c1, sweep, 4u * a + 1u, &u3, &u4);
             float c = (float)cos(2.0 * OR_PI * (double)u2);
             float l1 = (float)log((double)u1), l3 = (float)log((double)u3);
-            double lam2 = -((double)l1 + (double)(c * c) * (double)l3) * inv2a;
+            /* Kennedy-Pendleton: lambda^2 = -(ln u1 + cos^2(2 pi u2) ln u3) / (2 alpha),
+             * the single-precision logarithms and cosine taken into FP64 */
+            double lam2 = -((double)l1 + (double)(c * c) * (double)l3) / (2.0 * alpha);
             if (lam2 <= 1.0 && (double)u4 * (double)u4 <= 1.0 - lam2) {
                 x0 = 1.0 - 2.0 * lam2;
                 xlen = 2.0 * sqrt(lam2 * (1.0 - lam2));

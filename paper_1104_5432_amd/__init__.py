@@ -161,29 +161,58 @@ class Lattice:
         return ctypes.byref(self.desc)
 
 
+def _on_gpu(lat):
+    """The library's kernels address device memory: refuse a lattice whose
+    storage is not on a GPU before any call reaches them."""
+    if not lat.links.is_cuda:
+        raise ValueError(f"lattice storage must be on a GPU, not {lat.links.device}")
+    return lat
+
+
+def _tensor(t, lat, dtype, numel, name):
+    """Check a caller's output (or input) tensor before its address reaches
+    the library: on the lattice's device, of the given dtype, contiguous and
+    holding at least numel elements.  Returns t."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device != lat.links.device:
+        raise ValueError(f"{name} must be on {lat.links.device}, not {t.device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} must hold at least {numel} elements, not {t.numel()}")
+    return t
+
+
+def _rmax(lat):
+    return max(1, min(lat.n[:3]) // 2)
+
+
 def su2_init_cold(lat, stream=None):
-    _check(lib.su2_init_cold(lat.ref(), _stream(stream)))
+    _check(lib.su2_init_cold(_on_gpu(lat).ref(), _stream(stream)))
 
 
 def su2_init_hot(lat, seed, stream=None):
-    _check(lib.su2_init_hot(lat.ref(), int(seed), _stream(stream)))
+    _check(lib.su2_init_hot(_on_gpu(lat).ref(), int(seed), _stream(stream)))
 
 
 def su2_heatbath_sweep(lat, beta, seed, sweep, stream=None):
-    _check(lib.su2_heatbath_sweep(lat.ref(), float(beta), int(seed), int(sweep), _stream(stream)))
+    _check(lib.su2_heatbath_sweep(_on_gpu(lat).ref(), float(beta), int(seed), int(sweep), _stream(stream)))
 
 
 def su2_heatbath_halfsweep(lat, beta, seed, sweep, mu, parity, stream=None):
-    _check(lib.su2_heatbath_halfsweep(lat.ref(), float(beta), int(seed), int(sweep), int(mu), int(parity),
+    _check(lib.su2_heatbath_halfsweep(_on_gpu(lat).ref(), float(beta), int(seed), int(sweep), int(mu), int(parity),
                                       _stream(stream)))
 
 
 def su2_overrelax(lat, n_sweeps=1, stream=None):
-    _check(lib.su2_overrelax(lat.ref(), int(n_sweeps), _stream(stream)))
+    _check(lib.su2_overrelax(_on_gpu(lat).ref(), int(n_sweeps), _stream(stream)))
 
 
 def su2_overrelax_halfsweep(lat, mu, parity, stream=None):
-    _check(lib.su2_overrelax_halfsweep(lat.ref(), int(mu), int(parity), _stream(stream)))
+    _check(lib.su2_overrelax_halfsweep(_on_gpu(lat).ref(), int(mu), int(parity), _stream(stream)))
 
 
 def su2_plaquette(lat, out=None, stream=None):
@@ -191,7 +220,8 @@ def su2_plaquette(lat, out=None, stream=None):
     [mean, planes 01, 02, 03, 12, 13, 23]."""
     if out is None:
         out = torch.empty(7, dtype=torch.float64, device=lat.device)
-    _check(lib.su2_plaquette(lat.ref(), out.data_ptr(), _stream(stream)))
+    _tensor(out, lat, torch.float64, 7, "out")
+    _check(lib.su2_plaquette(_on_gpu(lat).ref(), out.data_ptr(), _stream(stream)))
     return out
 
 
@@ -201,8 +231,11 @@ def su2_polyakov(lat, out=None, corr=None, with_corr=True, stream=None):
     if out is None:
         out = torch.empty(2, dtype=torch.float64, device=lat.device)
     if corr is None and with_corr:
-        corr = torch.empty(max(1, min(lat.n[:3]) // 2), dtype=torch.float64, device=lat.device)
-    _check(lib.su2_polyakov(lat.ref(), out.data_ptr(), corr.data_ptr() if corr is not None else None,
+        corr = torch.empty(_rmax(lat), dtype=torch.float64, device=lat.device)
+    _tensor(out, lat, torch.float64, 2, "out")
+    if corr is not None:
+        _tensor(corr, lat, torch.float64, _rmax(lat), "corr")
+    _check(lib.su2_polyakov(_on_gpu(lat).ref(), out.data_ptr(), corr.data_ptr() if corr is not None else None,
                             _stream(stream)))
     return out, corr
 
@@ -212,7 +245,8 @@ def su2_heatbath_sweep_measured(lat, beta, seed, sweep, plaq=None, stream=None):
     su2_plaquette) of the configuration it produces; returns that tensor."""
     if plaq is None:
         plaq = torch.empty(7, dtype=torch.float64, device=lat.device)
-    _check(lib.su2_heatbath_sweep_measured(lat.ref(), float(beta), int(seed), int(sweep), plaq.data_ptr(),
+    _tensor(plaq, lat, torch.float64, 7, "plaq")
+    _check(lib.su2_heatbath_sweep_measured(_on_gpu(lat).ref(), float(beta), int(seed), int(sweep), plaq.data_ptr(),
                                            _stream(stream)))
     return plaq
 
@@ -222,7 +256,8 @@ def su2_overrelax_measured(lat, n_sweeps=1, plaq=None, stream=None):
     configuration; returns that tensor (7 float64)."""
     if plaq is None:
         plaq = torch.empty(7, dtype=torch.float64, device=lat.device)
-    _check(lib.su2_overrelax_measured(lat.ref(), int(n_sweeps), plaq.data_ptr(), _stream(stream)))
+    _tensor(plaq, lat, torch.float64, 7, "plaq")
+    _check(lib.su2_overrelax_measured(_on_gpu(lat).ref(), int(n_sweeps), plaq.data_ptr(), _stream(stream)))
     return plaq
 
 
@@ -234,8 +269,12 @@ def su2_measure(lat, plaq=None, poly=None, corr=None, with_corr=True, stream=Non
     if poly is None:
         poly = torch.empty(2, dtype=torch.float64, device=lat.device)
     if corr is None and with_corr:
-        corr = torch.empty(max(1, min(lat.n[:3]) // 2), dtype=torch.float64, device=lat.device)
-    _check(lib.su2_measure(lat.ref(), plaq.data_ptr(), poly.data_ptr(),
+        corr = torch.empty(_rmax(lat), dtype=torch.float64, device=lat.device)
+    _tensor(plaq, lat, torch.float64, 7, "plaq")
+    _tensor(poly, lat, torch.float64, 2, "poly")
+    if corr is not None:
+        _tensor(corr, lat, torch.float64, _rmax(lat), "corr")
+    _check(lib.su2_measure(_on_gpu(lat).ref(), plaq.data_ptr(), poly.data_ptr(),
                            corr.data_ptr() if corr is not None else None, _stream(stream)))
     return plaq, poly, corr
 
@@ -243,7 +282,8 @@ def su2_measure(lat, plaq=None, poly=None, corr=None, with_corr=True, stream=Non
 def su2_get_flags(lat, out=None, stream=None):
     if out is None:
         out = torch.empty(1, dtype=torch.int32, device=lat.device)
-    _check(lib.su2_get_flags(lat.ref(), out.data_ptr(), _stream(stream)))
+    _tensor(out, lat, torch.int32, 1, "out")
+    _check(lib.su2_get_flags(_on_gpu(lat).ref(), out.data_ptr(), _stream(stream)))
     return out
 
 
@@ -264,6 +304,13 @@ def su2_batch_fill(lattices, betas):
     return bytes(host), descs
 
 
+def _batch_on_gpu(batch):
+    for lat in batch.lattices:
+        _on_gpu(lat)
+    if batch.table.device != batch.lattices[0].links.device:
+        raise ValueError("the batch table must be on the lattices' device")
+
+
 class Batch:
     """Independent lattices of one precision updated together: the host table
     filled by su2_batch_fill, copied to a device tensor, plus the host array
@@ -282,11 +329,15 @@ class Batch:
 def su2_batch_heatbath_sweep(batch, seed, sweep=0, d_sweep=None, stream=None):
     """One heat-bath sweep of every lattice; the sweep index is d_sweep[0]
     (a device int32 tensor, read when the kernels run) if given, else sweep."""
+    _batch_on_gpu(batch)
+    if d_sweep is not None:
+        _tensor(d_sweep, batch.lattices[0], torch.int32, 1, "d_sweep")
     _check(lib.su2_batch_heatbath_sweep(batch.descs, batch.count, batch.table.data_ptr(), int(seed), int(sweep),
                                         d_sweep.data_ptr() if d_sweep is not None else None, _stream(stream)))
 
 
 def su2_batch_overrelax(batch, n_sweeps=1, stream=None):
+    _batch_on_gpu(batch)
     _check(lib.su2_batch_overrelax(batch.descs, batch.count, batch.table.data_ptr(), int(n_sweeps),
                                    _stream(stream)))
 
@@ -311,6 +362,9 @@ def su2_batch_polyakov(batch, poly=None, corr=None, with_corr=True, stream=None)
             raise ValueError("corr must be a float64 tensor of shape (count, >= max min(Nx,Ny,Nz)/2) with unit "
                              "column stride")
         stride = corr.stride(0)
+    if poly.device != dev or (corr is not None and corr.device != dev):
+        raise ValueError(f"poly and corr must be on {dev}")
+    _batch_on_gpu(batch)
     _check(lib.su2_batch_polyakov(batch.descs, batch.count, batch.table.data_ptr(), poly.data_ptr(),
                                   corr.data_ptr() if corr is not None else None, int(stride), _stream(stream)))
     return poly, corr
@@ -318,6 +372,9 @@ def su2_batch_polyakov(batch, poly=None, corr=None, with_corr=True, stream=None)
 
 def su2_sweep_advance(d_sweep, stream=None):
     """d_sweep[0] += 1 on the device."""
+    if not isinstance(d_sweep, torch.Tensor) or not d_sweep.is_cuda or d_sweep.dtype != torch.int32 \
+            or d_sweep.numel() < 1:
+        raise ValueError("d_sweep must be an int32 tensor on a GPU with at least one element")
     _check(lib.su2_sweep_advance(d_sweep.data_ptr(), _stream(stream)))
 
 
@@ -343,11 +400,19 @@ class LPWork:
         self.buf = torch.empty(nb, dtype=torch.uint8, device=device)
 
 
+def _lp_inputs(lat, params, lpwork):
+    _tensor(params, lat, torch.float32, su2_lp_param_count(), "params")
+    if lpwork.buf.device != lat.links.device or lpwork.n != lat.n:
+        raise ValueError("lpwork must be made for this lattice's extents, on its device")
+
+
 def su2_lp_forward(lat, params, lpwork, y=None, stream=None):
     """Network outputs y[site*6 + d] (device float32) for the current links."""
     if y is None:
         y = torch.empty(lat.volume * 6, dtype=torch.float32, device=lat.device)
-    _check(lib.su2_lp_forward(lat.ref(), params.data_ptr(), lpwork.buf.data_ptr(), lpwork.buf.numel(),
+    _lp_inputs(lat, params, lpwork)
+    _tensor(y, lat, torch.float32, lat.volume * 6, "y")
+    _check(lib.su2_lp_forward(_on_gpu(lat).ref(), params.data_ptr(), lpwork.buf.data_ptr(), lpwork.buf.numel(),
                               y.data_ptr(), _stream(stream)))
     return y
 
@@ -357,24 +422,36 @@ def su2_lp_loss_grad(lat, beta, params, lpwork, grad=None, loss=None, stream=Non
         grad = torch.empty(su2_lp_param_count(), dtype=torch.float32, device=lat.device)
     if loss is None:
         loss = torch.empty(1, dtype=torch.float64, device=lat.device)
-    _check(lib.su2_lp_loss_grad(lat.ref(), float(beta), params.data_ptr(), lpwork.buf.data_ptr(),
+    _lp_inputs(lat, params, lpwork)
+    _tensor(grad, lat, torch.float32, su2_lp_param_count(), "grad")
+    _tensor(loss, lat, torch.float64, 1, "loss")
+    _check(lib.su2_lp_loss_grad(_on_gpu(lat).ref(), float(beta), params.data_ptr(), lpwork.buf.data_ptr(),
                                 lpwork.buf.numel(), grad.data_ptr(), loss.data_ptr(), _stream(stream)))
     return grad, loss
 
 
 def su2_lp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    for name, t in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        if (not isinstance(t, torch.Tensor) or not t.is_cuda or t.device != params.device
+                or t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != params.numel()):
+            raise ValueError(f"{name} must be a contiguous float32 tensor on params' GPU with params.numel() "
+                             "elements")
     _check(lib.su2_lp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), params.numel(),
                            int(step), float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
 
 
 def su2_lp_move(lat, beta, seed, step, parity, colour, y, accepted, stream=None):
-    _check(lib.su2_lp_move(lat.ref(), float(beta), int(seed), int(step), int(parity), int(colour), y.data_ptr(),
+    _tensor(y, lat, torch.float32, lat.volume * 6, "y")
+    _tensor(accepted, lat, torch.int32, 1, "accepted")
+    _check(lib.su2_lp_move(_on_gpu(lat).ref(), float(beta), int(seed), int(step), int(parity), int(colour), y.data_ptr(),
                            accepted.data_ptr(), _stream(stream)))
 
 
 def su2_lp_sweep(lat, beta, seed, step, y, accepted, stream=None):
     """All 16 block classes with network outputs y; accepted[0] += accepted moves."""
-    _check(lib.su2_lp_sweep(lat.ref(), float(beta), int(seed), int(step), y.data_ptr(), accepted.data_ptr(),
+    _tensor(y, lat, torch.float32, lat.volume * 6, "y")
+    _tensor(accepted, lat, torch.int32, 1, "accepted")
+    _check(lib.su2_lp_sweep(_on_gpu(lat).ref(), float(beta), int(seed), int(step), y.data_ptr(), accepted.data_ptr(),
                             _stream(stream)))
 
 

@@ -4,9 +4,12 @@
 #include "su2_launch.hpp"
 #include "su2_learned.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <utility>
+#include <vector>
 
 namespace {
 
@@ -43,6 +46,12 @@ bool aligned(const void *p, uintptr_t a)
     return ((uintptr_t)p % a) == 0;
 }
 
+uint64_t links_bytes_of(const int32_t n[4], int32_t prec)
+{
+    const uint64_t vol = (uint64_t)n[0] * n[1] * n[2] * n[3];
+    return vol * 4u * (prec == SU2_F32 ? 16u : 32u);
+}
+
 // Common checks of a lattice descriptor.
 int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayout *wl)
 {
@@ -65,6 +74,12 @@ int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayou
     const su2::WorkLayout w = su2::work_layout(lat->n);
     if (lat->work_bytes < w.total)
         return fail(SU2_EWORK, "work_bytes is smaller than su2_workspace_bytes()");
+    {
+        const uintptr_t l0 = (uintptr_t)lat->links, l1 = l0 + links_bytes_of(lat->n, lat->prec);
+        const uintptr_t w0 = (uintptr_t)lat->work, w1 = w0 + w.total;
+        if (l0 < w1 && w0 < l1)
+            return fail(SU2_EINVAL, "links and work must not overlap");
+    }
     out->n[0] = lat->n[0];
     out->n[1] = lat->n[1];
     out->n[2] = lat->n[2];
@@ -137,6 +152,27 @@ int check_batch(const su2_lattice_t *lats, int32_t count, uint32_t *total)
     }
     if (sum >= (1ull << 31))
         return fail(SU2_EDIMS, "a batch must have fewer than 2^31 blocks per class");
+    // Distinct lattices: one launch updates every lattice's class at once, so
+    // shared links would race, a shared workspace would mix two lattices'
+    // flags and partials, and a repeated lattice id would repeat a random
+    // stream.
+    std::vector<std::pair<uintptr_t, uintptr_t>> spans;
+    std::vector<int32_t> ids;
+    spans.reserve(2 * (size_t)count);
+    ids.reserve((size_t)count);
+    for (int j = 0; j < count; ++j) {
+        const uintptr_t l0 = (uintptr_t)lats[j].links, w0 = (uintptr_t)lats[j].work;
+        spans.emplace_back(l0, l0 + links_bytes_of(lats[j].n, lats[j].prec));
+        spans.emplace_back(w0, w0 + su2::work_layout(lats[j].n).total);
+        ids.push_back(lats[j].lattice_id);
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+        if (spans[k].first < spans[k - 1].second)
+            return fail(SU2_EINVAL, "the lattices of a batch must not share or overlap links or work");
+    std::sort(ids.begin(), ids.end());
+    if (std::adjacent_find(ids.begin(), ids.end()) != ids.end())
+        return fail(SU2_EINVAL, "the lattices of a batch must have distinct lattice ids");
     if (total)
         *total = (uint32_t)sum;
     return SU2_OK;
@@ -188,8 +224,7 @@ uint64_t su2_links_bytes(const int32_t n[4], int32_t prec)
 {
     if (!dims_ok(n) || !prec_ok(prec))
         return 0;
-    const uint64_t vol = (uint64_t)n[0] * n[1] * n[2] * n[3];
-    return vol * 4u * (prec == SU2_F32 ? 16u : 32u);
+    return links_bytes_of(n, prec);
 }
 
 uint64_t su2_workspace_bytes(const int32_t n[4], int32_t prec)

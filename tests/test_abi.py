@@ -51,7 +51,7 @@ def test_sizes(su2):
     assert su2.su2_links_bytes((256, 256, 256, 254), "f32") > 0
 
 
-def _desc(su2, n=(8, 8, 8, 8), prec=0, lid=0, links=0x10000, work=0x20000, wb=None, tile=0, tile_y=0):
+def _desc(su2, n=(8, 8, 8, 8), prec=0, lid=0, links=0x10000000, work=0x20000000, wb=None, tile=0, tile_y=0):
     if wb is None:
         wb = su2.su2_workspace_bytes(n, 0) if all(v >= 2 and v % 2 == 0 for v in n) else 1 << 20
     return su2.su2_lattice_t((ctypes.c_int32 * 4)(*n), prec, lid, tile, tile_y, links, work, wb)
@@ -75,8 +75,8 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     # null and misaligned pointers
     assert L.su2_init_hot(by(_desc(su2, links=0)), 1, s) == su2.SU2_EINVAL
     assert L.su2_init_hot(by(_desc(su2, work=0)), 1, s) == su2.SU2_EINVAL
-    assert L.su2_init_hot(by(_desc(su2, links=0x10008)), 1, s) == su2.SU2_EALIGN
-    assert L.su2_init_hot(by(_desc(su2, work=0x20004)), 1, s) == su2.SU2_EALIGN
+    assert L.su2_init_hot(by(_desc(su2, links=0x10000008)), 1, s) == su2.SU2_EALIGN
+    assert L.su2_init_hot(by(_desc(su2, work=0x20000004)), 1, s) == su2.SU2_EALIGN
     # workspace too small
     need = su2.su2_workspace_bytes((8, 8, 8, 8), 0)
     assert L.su2_plaquette(by(_desc(su2, wb=need - 1)), 0x30000, s) == su2.SU2_EWORK
@@ -112,13 +112,23 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     for ty in (-1, 3, 16):
         assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 12, 8), tile_y=ty)), s) == su2.SU2_EINVAL
     # batches
-    d0, d1 = _desc(su2), _desc(su2, n=(4, 4, 4, 6), lid=1)
+    # links and work of one lattice must not overlap
+    assert L.su2_init_cold(by(_desc(su2, links=0x10000000, work=0x10000000 + 4096)), s) == su2.SU2_EINVAL
+    d0, d1 = _desc(su2), _desc(su2, n=(4, 4, 4, 6), lid=1, links=0x30000000, work=0x40000000)
     arr = (su2.su2_lattice_t * 2)(d0, d1)
     betas = (ctypes.c_double * 2)(2.3, 2.4)
     nb = L.su2_batch_table_bytes(2)
     assert nb > 0 and L.su2_batch_table_bytes(0) == 0 and L.su2_batch_table_bytes(4097) == 0
     host = (ctypes.c_char * nb)()
     assert L.su2_batch_fill(arr, betas, 2, host, nb) == su2.SU2_OK      # host-only call
+    # distinct lattices: no shared or overlapping links or work, distinct ids
+    for other in (_desc(su2, n=(4, 4, 4, 6), lid=1, links=0x10000000 + 256, work=0x40000000),
+                  _desc(su2, n=(4, 4, 4, 6), lid=1, links=0x30000000, work=0x20000000),
+                  _desc(su2, n=(4, 4, 4, 6), lid=1, links=0x30000000, work=0x10000000 + 4096),
+                  _desc(su2, n=(4, 4, 4, 6), lid=0, links=0x30000000, work=0x40000000)):
+        dup = (su2.su2_lattice_t * 2)(d0, other)
+        assert L.su2_batch_fill(dup, betas, 2, host, nb) == su2.SU2_EINVAL
+        assert L.su2_batch_overrelax(dup, 2, 0x40000, 1, s) == su2.SU2_EINVAL
     assert L.su2_batch_fill(arr, betas, 2, host, nb - 1) == su2.SU2_EWORK
     assert L.su2_batch_fill(arr, betas, 0, host, nb) == su2.SU2_EINVAL
     assert L.su2_batch_fill(None, betas, 2, host, nb) == su2.SU2_EINVAL
@@ -194,3 +204,84 @@ def test_batch_polyakov_binding_checks_its_tensors(su2):
                  torch.zeros((2, 8), dtype=torch.float64)[:, ::2]):
         with pytest.raises(ValueError):
             su2.su2_batch_polyakov(batch, poly=good_poly, corr=corr)
+
+
+def test_binding_checks_tensors_before_the_library(su2):
+    # every wrapper refuses an output of the wrong device, dtype, layout or
+    # size, and a lattice that is not in GPU memory, before any library call
+    import torch
+    lat = su2.Lattice((8, 8, 8, 4), "f64", device="cpu")
+    f64 = torch.float64
+
+    def bad(numel, dtype=f64):
+        ts = [torch.zeros(numel - 1, dtype=dtype),                             # too short
+              torch.zeros(numel, dtype=torch.float32 if dtype != torch.float32 else f64),
+              torch.zeros(numel, dtype=dtype, device="meta")]                  # another device
+        if numel > 1:                                                          # not contiguous
+            ts.append(torch.zeros(2 * numel, dtype=dtype)[::2])
+        return ts
+
+    for t in bad(7):
+        for call in (lambda: su2.su2_plaquette(lat, t),
+                     lambda: su2.su2_heatbath_sweep_measured(lat, 2.3, 1, 0, t),
+                     lambda: su2.su2_overrelax_measured(lat, 1, t),
+                     lambda: su2.su2_measure(lat, plaq=t)):
+            with pytest.raises(ValueError, match="^(out|plaq) must"):
+                call()
+    for t in bad(2):
+        with pytest.raises(ValueError, match="^out must"):
+            su2.su2_polyakov(lat, out=t, with_corr=False)
+        with pytest.raises(ValueError, match="^poly must"):
+            su2.su2_measure(lat, poly=t, with_corr=False)
+    for t in bad(4):                               # min(Nx,Ny,Nz)/2 = 4 separations
+        with pytest.raises(ValueError, match="^corr must"):
+            su2.su2_polyakov(lat, corr=t)
+        with pytest.raises(ValueError, match="^corr must"):
+            su2.su2_measure(lat, corr=t)
+    for t in bad(1, torch.int32):
+        with pytest.raises(ValueError, match="^out must"):
+            su2.su2_get_flags(lat, t)
+    # correct tensors pass those checks; the host lattice is then refused
+    for call in (lambda: su2.su2_plaquette(lat, torch.zeros(7, dtype=f64)),
+                 lambda: su2.su2_polyakov(lat),
+                 lambda: su2.su2_measure(lat),
+                 lambda: su2.su2_get_flags(lat),
+                 lambda: su2.su2_init_cold(lat),
+                 lambda: su2.su2_init_hot(lat, 1),
+                 lambda: su2.su2_heatbath_sweep(lat, 2.3, 1, 0),
+                 lambda: su2.su2_heatbath_halfsweep(lat, 2.3, 1, 0, 0, 0),
+                 lambda: su2.su2_overrelax(lat, 1),
+                 lambda: su2.su2_overrelax_halfsweep(lat, 0, 0),
+                 lambda: su2.su2_heatbath_sweep_measured(lat, 2.3, 1, 0),
+                 lambda: su2.su2_overrelax_measured(lat, 1)):
+        with pytest.raises(ValueError, match="on a GPU"):
+            call()
+    # learned proposal
+    y = torch.zeros(lat.volume * 6, dtype=torch.float32)
+    acc = torch.zeros(1, dtype=torch.int32)
+    for t in bad(lat.volume * 6, torch.float32):
+        with pytest.raises(ValueError, match="^y must"):
+            su2.su2_lp_sweep(lat, 2.3, 1, 0, t, acc)
+        with pytest.raises(ValueError, match="^y must"):
+            su2.su2_lp_move(lat, 2.3, 1, 0, 0, 0, t, acc)
+    for t in bad(1, torch.int32):
+        with pytest.raises(ValueError, match="^accepted must"):
+            su2.su2_lp_sweep(lat, 2.3, 1, 0, y, t)
+    with pytest.raises(ValueError, match="on a GPU"):
+        su2.su2_lp_sweep(lat, 2.3, 1, 0, y, acc)
+    p = torch.zeros(su2.su2_lp_param_count(), dtype=torch.float32)
+    for t in (p[:-1], p.double(), torch.zeros(2 * p.numel(), dtype=torch.float32)[::2]):
+        with pytest.raises(ValueError):
+            su2.su2_lp_adam(p, t, p, p, 1)
+    with pytest.raises(ValueError):                # host tensors are refused too
+        su2.su2_lp_adam(p, p.clone(), p.clone(), p.clone(), 1)
+    # batches: host lattices and a d_sweep of the wrong type
+    lats = [su2.Lattice((8, 8, 8, 4), "f32", device="cpu", lattice_id=0),
+            su2.Lattice((4, 4, 4, 6), "f32", device="cpu", lattice_id=1)]
+    batch = su2.Batch(lats, [2.3, 2.4])
+    with pytest.raises(ValueError, match="on a GPU"):
+        su2.su2_batch_overrelax(batch, 1)
+    with pytest.raises(ValueError, match="on a GPU"):
+        su2.su2_batch_heatbath_sweep(batch, 1, 0)
+    with pytest.raises(ValueError):
+        su2.su2_sweep_advance(torch.zeros(1, dtype=torch.int32))

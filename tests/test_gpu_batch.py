@@ -125,6 +125,36 @@ def test_batch_members_match_oracle(su2):
             assert err <= 1e-12, (lat.n, s, err)
 
 
+def test_batch_scan_shapes_match_oracle(su2):
+    # The temperature scan's three shapes (32^3x4, 48^3x6, 64^3x8) as scan
+    # members j = 0, 7, 14 (shape j mod 3, beta_j = 2.2 + 0.5 j / 15,
+    # lattice_id j), FP64, in one batch: one heat-bath sweep and one
+    # overrelaxation sweep, per link against the oracle chain of each.
+    seed = 1234
+    members = (0, 7, 14)
+    scan_shapes = [(32, 32, 32, 4), (48, 48, 48, 6), (64, 64, 64, 8)]
+    shapes = [scan_shapes[j % 3] for j in members]
+    betas = [2.2 + 0.5 * j / 15 for j in members]
+    print("batched scan shapes", shapes, "betas", [round(b, 4) for b in betas], flush=True)
+    lats = [su2.Lattice(n, "f64", device="cuda", lattice_id=j) for n, j in zip(shapes, members)]
+    for lat in lats:
+        su2.su2_init_hot(lat, seed)
+    batch = su2.Batch(lats, betas)
+    su2.su2_batch_heatbath_sweep(batch, seed, sweep=0)
+    su2.su2_batch_overrelax(batch, 1)
+    _sync()
+    for lat, n, beta, j in zip(lats, shapes, betas, members):
+        ref = oracle.init_hot(n, seed, lattice_id=j)
+        assert oracle.heatbath_sweep(n, ref, beta, seed, 0, lattice_id=j) == 0
+        oracle.overrelax_sweep(n, ref)
+        err = float(np.max(np.abs(su2.to_canonical(lat).numpy() - ref)))
+        print(f"  {n} beta {beta:.4f} id {j}: max |dU| = {err:.2e}", flush=True)
+        assert err <= 1e-12, (n, err)
+        f = su2.su2_get_flags(lat)
+        _sync()
+        assert int(f.item()) == 0
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_graph_replay_matches_eager(su2, prec):
     seed, n_or, replays = 2024, 2, 5

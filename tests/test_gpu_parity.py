@@ -12,9 +12,11 @@ Tolerances:
   factors; every single class and every re-synchronised sweep meets 1e-12.
 - Observables on identical configurations: FP64 sums, <= 1e-13 relative
   (different, fixed summation orders).
-- FP32 links: after one half-sweep from the same (rounded) configuration,
-  <= 5e-5 per link (FP32 staples, 23-bit uniforms) except links whose
-  accept/reject decision flips between the 23-bit and the 52-bit uniforms.
+- FP32 links: every heat-bath class against the oracle's single-precision
+  step from the same configuration (the accept/reject decisions taken in
+  the same precisions): at most one link per class may decide differently,
+  every other link agrees to 2e-6; overrelaxation classes against the FP64
+  oracle on the same FP32 configuration to 2e-6 (no decisions).
 - Ensembles (FP32 vs FP64 chains): means within 3 sigma (Gamma-method
   errors), 2-sigma excursions reported.
 """
@@ -62,6 +64,43 @@ def _flags(su2, lat):
     f = su2.su2_get_flags(lat)
     _sync()
     return int(f.item())
+
+
+def _fp32_class_against_single_precision_oracle(su2, lat, n, beta, seed, sweep, mu, par):
+    """One FP32 heat-bath class on the GPU against the oracle's
+    single-precision step from the same configuration: at most one link may
+    take a different accept/reject decision (a test landing within the
+    last-ulp differences of the two sides' FP32 staples and logarithms), every
+    other link agrees to 2e-6 (FP32 rounding of staple, direction and
+    product), and every link is a unit quaternion.  Returns the GPU's links."""
+    ref = su2.to_canonical(lat).numpy()
+    assert oracle.heatbath_halfsweep_f32(n, ref, beta, seed, sweep, mu, par) == 0
+    su2.su2_heatbath_halfsweep(lat, beta, seed, sweep, mu, par)
+    _sync()
+    got = su2.to_canonical(lat).numpy()
+    d = np.max(np.abs(got - ref), axis=-1)
+    del ref
+    flips = int(np.sum(d > 2e-6))
+    print(f"  class ({mu},{par}) beta {beta}: {flips} decision(s) differ, "
+          f"max |dU| of the others {float(np.max(np.where(d > 2e-6, 0, d))):.2e}", flush=True)
+    assert flips <= 1, (mu, par, np.sort(d.ravel())[-3:])
+    del d
+    assert np.max(np.abs((got * got).sum(-1) - 1.0)) <= 6e-7
+    return got
+
+
+def _fp32_or_class_against_oracle(su2, lat, n, mu, par, start):
+    """One FP32 overrelaxation class against the FP64 oracle's on the same
+    FP32 configuration: deterministic, so 2e-6 per link."""
+    ref = start.copy()
+    oracle.overrelax_halfsweep(n, ref, mu, par)
+    su2.su2_overrelax_halfsweep(lat, mu, par)
+    _sync()
+    got = su2.to_canonical(lat).numpy()
+    err = _maxdiff(got, ref)
+    del ref
+    assert err <= 2e-6, (mu, par, err)
+    return got
 
 
 # ---------------------------------------------------------------------------
@@ -192,13 +231,7 @@ def test_fp32_halfsweep_close_to_oracle(su2):
     for s in range(3):
         oracle.heatbath_sweep(n, U0, beta, 3, s)
     lat = _lat(su2, n, "f32", U0)
-    U32 = su2.to_canonical(lat).numpy()           # the FP32-rounded start
-    ref = U32.copy()
-    oracle.heatbath_halfsweep(n, ref, beta, seed, 4, 1, 0)
-    su2.su2_heatbath_halfsweep(lat, beta, seed, 4, 1, 0)
-    _sync()
-    d = np.max(np.abs(su2.to_canonical(lat).numpy() - ref), axis=-1)
-    assert np.mean(d > 5e-5) <= 1e-3, np.sort(d.ravel())[-5:]
+    _fp32_class_against_single_precision_oracle(su2, lat, n, beta, seed, 4, 1, 0)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -212,15 +245,14 @@ def test_heatbath_degenerate_couplings_match_oracle(su2, prec, beta):
     for s in range(2):
         oracle.heatbath_sweep(n, U0, 2.3, seed, s)
     lat = _lat(su2, n, prec, U0)
-    ref = su2.to_canonical(lat).numpy()            # the start the GPU holds
-    oracle.heatbath_halfsweep(n, ref, beta, seed, 2, 2, 1)
-    su2.su2_heatbath_halfsweep(lat, beta, seed, 2, 2, 1)
-    _sync()
-    d = np.max(np.abs(su2.to_canonical(lat).numpy() - ref), axis=-1)
     if prec == "f64":
-        assert d.max() <= 1e-12
+        ref = su2.to_canonical(lat).numpy()        # the start the GPU holds
+        oracle.heatbath_halfsweep(n, ref, beta, seed, 2, 2, 1)
+        su2.su2_heatbath_halfsweep(lat, beta, seed, 2, 2, 1)
+        _sync()
+        assert _maxdiff(su2.to_canonical(lat).numpy(), ref) <= 1e-12
     else:
-        assert np.mean(d > 5e-5) <= 1e-3 and np.median(d) < 1e-6, np.sort(d.ravel())[-5:]
+        _fp32_class_against_single_precision_oracle(su2, lat, n, beta, seed, 2, 2, 1)
     assert _flags(su2, lat) == 0
 
 
@@ -240,14 +272,7 @@ def test_fp32_heatbath_matches_single_precision_oracle(su2, n, beta):
     lat = _lat(su2, n, "f32", U0)
     for mu in range(4):
         for par in range(2):
-            ref = su2.to_canonical(lat).numpy()
-            assert oracle.heatbath_halfsweep_f32(n, ref, beta, 12, 5, mu, par) == 0
-            su2.su2_heatbath_halfsweep(lat, beta, 12, 5, mu, par)
-            _sync()
-            got = su2.to_canonical(lat).numpy()
-            d = np.max(np.abs(got - ref), axis=-1)
-            assert np.sum(d > 2e-6) <= 1, (mu, par, np.sort(d.ravel())[-3:])
-            assert np.max(np.abs((got * got).sum(-1) - 1.0)) <= 6e-7
+            _fp32_class_against_single_precision_oracle(su2, lat, n, beta, 12, 5, mu, par)
     assert _flags(su2, lat) == 0
 
 
@@ -488,10 +513,10 @@ def test_observables_gauge_invariant_on_gpu(su2):
 # ---------------------------------------------------------------------------
 # full size (64^4), the configuration the benchmark times
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_full_size_64(su2, prec):
-    n, beta, seed = (64, 64, 64, 64), 2.3, 1234
-    print(f"full-size parity {n} {prec}", flush=True)
+@pytest.mark.parametrize("prec,beta", [("f32", 2.3), ("f64", 2.3), ("f64", 2.5), ("f64", 6.0)])
+def test_full_size_64(su2, prec, beta):
+    n, seed = (64, 64, 64, 64), 1234
+    print(f"full-size parity {n} {prec} beta {beta}", flush=True)
     ref = oracle.init_hot(n, seed)
     # the walk the benchmark uses at this size (shipped tuning table)
     lat = su2.Lattice(n, prec, device="cuda", tile=8, tile_y=8)
@@ -499,23 +524,22 @@ def test_full_size_64(su2, prec):
     _sync()
     tol_start = 1e-15 if prec == "f64" else 2e-7
     assert _maxdiff(su2.to_canonical(lat).numpy(), ref) <= tol_start
-    if prec == "f32":
-        ref = su2.to_canonical(lat).numpy()
     # one heat-bath class with the t wrap-around, one overrelaxation class
-    oracle.heatbath_halfsweep(n, ref, beta, seed, 0, 3, 1)
-    su2.su2_heatbath_halfsweep(lat, beta, seed, 0, 3, 1)
-    oracle.overrelax_halfsweep(n, ref, 0, 0)
-    su2.su2_overrelax_halfsweep(lat, 0, 0)
+    if prec == "f64":
+        oracle.heatbath_halfsweep(n, ref, beta, seed, 0, 3, 1)
+        su2.su2_heatbath_halfsweep(lat, beta, seed, 0, 3, 1)
+        oracle.overrelax_halfsweep(n, ref, 0, 0)
+        su2.su2_overrelax_halfsweep(lat, 0, 0)
+        _sync()
+        got = su2.to_canonical(lat).numpy()
+        assert _maxdiff(got, ref) <= 1e-13
+    else:
+        got = _fp32_class_against_single_precision_oracle(su2, lat, n, beta, seed, 0, 3, 1)
+        got = _fp32_or_class_against_oracle(su2, lat, n, 0, 0, got)
+    del ref
     plaq = su2.su2_plaquette(lat)
     poly, corr = su2.su2_polyakov(lat)
     _sync()
-    got = su2.to_canonical(lat).numpy()
-    d = np.max(np.abs(got - ref), axis=-1)
-    if prec == "f64":
-        assert d.max() <= 1e-13
-    else:
-        assert np.mean(d > 5e-5) <= 1e-4 and np.median(d) < 1e-6
-    del ref
     p, planes = oracle.plaquette(n, got)
     lm, la = oracle.polyakov(n, got)
     tol = 1e-13 if prec == "f64" else 1e-6
@@ -529,6 +553,34 @@ def test_full_size_64(su2, prec):
     sep = su2.su2_plaquette(lat)
     _sync()
     assert _maxdiff(m.cpu().numpy(), sep.cpu().numpy()) <= (1e-14 if prec == "f64" else 1e-6)
+    assert _flags(su2, lat) == 0
+
+
+@pytest.mark.parametrize("n", [(8, 8, 8, 8), (16, 8, 8, 4)])
+@pytest.mark.parametrize("beta", [2.3, 2.5, 6.0])
+def test_chained_benchmark_step_matches_oracle(su2, n, beta):
+    # The unit the benchmark times, 1 heat-bath + 4 overrelaxation sweeps,
+    # chained on the GPU and on the oracle from the same thermalised FP64
+    # configuration, per link to 1e-12.  The oracle alone, against a copy of
+    # its input perturbed by 1e-16, moves by 2.4e-13 (beta 2.3), 1e-13 (2.5)
+    # and 1e-14 (6.0) over such a step on 8^4; the GPU and the oracle differ
+    # by rounding of the same size at every operation.
+    # (8^4: coordinate-addressed kernels; 16x8x8x4: column-addressed.)
+    seed = 1234
+    U0 = oracle.init_hot(n, seed)
+    for s in range(10):
+        oracle.heatbath_sweep(n, U0, beta, seed, 100 + s)
+    ref = U0.copy()
+    lat = _lat(su2, n, "f64", U0)
+    oracle.heatbath_sweep(n, ref, beta, seed, 0)
+    for _ in range(4):
+        oracle.overrelax_sweep(n, ref)
+    su2.su2_heatbath_sweep(lat, beta, seed, 0)
+    su2.su2_overrelax(lat, 4)
+    _sync()
+    err = _maxdiff(su2.to_canonical(lat).numpy(), ref)
+    print(f"{n} beta {beta}: 1 HB + 4 OR chained, max |dU| = {err:.2e}", flush=True)
+    assert err <= 1e-12, err
     assert _flags(su2, lat) == 0
 
 
@@ -651,25 +703,18 @@ def test_max_size_96_cold_start(su2):
     # the walk the benchmark uses at this size (shipped tuning table)
     lat = su2.Lattice(n, "f32", device="cuda", tile=96, tile_y=8)
     su2.su2_init_cold(lat)
-    ref = oracle.init_cold(n)
     # a heat-bath class that wraps in t and reads the last planes of the
-    # buffer (offsets beyond 4 GiB), then an overrelaxation class
-    oracle.heatbath_halfsweep(n, ref, beta, seed, 0, 3, 1)
-    su2.su2_heatbath_halfsweep(lat, beta, seed, 0, 3, 1)
-    oracle.overrelax_halfsweep(n, ref, 0, 0)
-    su2.su2_overrelax_halfsweep(lat, 0, 0)
+    # buffer (offsets beyond 4 GiB) against the oracle's single-precision
+    # step, then an overrelaxation class against the FP64 oracle's on the
+    # configuration the GPU holds
+    got = _fp32_class_against_single_precision_oracle(su2, lat, n, beta, seed, 0, 3, 1)
+    got = _fp32_or_class_against_oracle(su2, lat, n, 0, 0, got)
     plaq = su2.su2_plaquette(lat)
     poly, corr = su2.su2_polyakov(lat)
     _sync()
-    got = su2.to_canonical(lat).numpy()
-    d = np.max(np.abs(got - ref), axis=-1)
-    del ref
-    # FP32 links against FP64: rounding, plus rare accept/reject flips of
-    # 23-bit against 52-bit uniforms
-    assert np.mean(d > 5e-5) <= 1e-4 and np.median(d) < 1e-6, (np.mean(d > 5e-5), np.median(d))
-    del d
     p, planes = oracle.plaquette(n, got)
     lm, la = oracle.polyakov(n, got)
+    del got
     g = plaq.cpu().numpy()
     assert abs(g[0] - p) <= 1e-6 and _maxdiff(g[1:], planes) <= 1e-6
     g = poly.cpu().numpy()
