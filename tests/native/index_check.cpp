@@ -152,8 +152,12 @@ int main()
                                {16, 8, 8, 4},  {24, 16, 6, 6}, {8, 16, 4, 2}};
     for (const auto &n : full)
         check_shape(n, 1);
-    const int32_t big[][4] = {{16, 16, 16, 16}, {32, 32, 32, 4}, {48, 48, 48, 6}, {64, 64, 64, 8},
-                              {64, 64, 64, 64}, {96, 96, 96, 96}};
+    // up to the largest the API accepts: V/2 = 2^28 (the last column-
+    // addressed size: byte offsets of a plane just fit 32 bits), V/2 > 2^28
+    // (coordinate addressing), and V just under 2^32 (the 32-bit site index)
+    const int32_t big[][4] = {{16, 16, 16, 16}, {32, 32, 32, 4},    {48, 48, 48, 6},    {64, 64, 64, 8},
+                              {64, 64, 64, 64}, {96, 96, 96, 96},   {128, 128, 128, 256}, {160, 160, 160, 160},
+                              {256, 256, 256, 254}, {254, 256, 256, 256}};
     for (const auto &n : big)
         check_shape(n, 99991);
     for (uint32_t nb = 1; nb < 3000; nb += 7) {

@@ -4,8 +4,9 @@ tests/native/index_check.cpp includes the kernels' own device header and
 runs its index functions (walk order, checkerboard coordinates, both
 neighbour-addressing policies, the XCD block renumbering) on the CPU against
 plain coordinate arithmetic, for every walk mode and a range of shapes up to
-96^4.  An index error in the kernels would be an out-of-bounds access on the
-GPU; this catches it without one.
+the largest the API accepts (V just below 2^32).  An index error in the
+kernels would be an out-of-bounds access on the GPU; this catches it
+without one.
 """
 import os
 import shutil
