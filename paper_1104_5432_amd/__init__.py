@@ -347,7 +347,7 @@ def su2_batch_polyakov(batch, poly=None, corr=None, with_corr=True, stream=None)
     as su2_polyakov of each.  Returns (poly [count, 2] float64, corr
     [count, stride] float64 or None); row j of corr holds C(r), r = 1..
     min(Nx,Ny,Nz)/2 of lattice j, and is left untouched beyond."""
-    dev = batch.lattices[0].device
+    dev = batch.lattices[0].links.device
     rmax = max(min(lat.n[:3]) // 2 for lat in batch.lattices)
     stride = rmax
     if poly is None:
