@@ -138,6 +138,21 @@ int su2_overrelax_halfsweep(const su2_lattice_t *lat, int32_t mu, int32_t parity
  * reduction order is fixed, so the result is bitwise reproducible. */
 int su2_plaquette(const su2_lattice_t *lat, double *d_out, void *stream);
 
+/* su2_plaquette for callers that cannot allocate device memory or hand the
+ * library a workspace (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and the same d_out,
+ * bitwise the same result, but the block partials go to a static 8 MiB
+ * array of the library on the current device instead of lat->work, which
+ * is not used (work and work_bytes may be NULL and 0).  No allocation, no
+ * free.  Limit: V/2 <= 256 x 174762 = 44,739,072 sites per parity (96^4 fits);
+ * larger lattices give SU2_EDIMS.  The current device must be the one that
+ * holds the links, d_out and the stream.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap in time on one GPU (different streams
+ * or threads) race; calls ordered on one stream do not.  Errors: as
+ * su2_plaquette except for the workspace; SU2_EHIP if the array's address
+ * cannot be obtained. */
+int su2_plaquette_noalloc(const su2_lattice_t *lat, double *d_out, void *stream);
+
 /* Polyakov loop (Sec. 2.2, eq. (1)) L(x) = (1/2) Tr prod_{t=0}^{Nt-1}
  * U_t(x,t) at every spatial site.  d_out (device, 2 doubles) receives
  * [0] the spatial mean of L and [1] the spatial mean of |L|.  If d_corr is

@@ -60,6 +60,7 @@ _SIGNATURES = {
     "su2_overrelax": (ctypes.c_int, [_LP, ctypes.c_int32, _VP]),
     "su2_overrelax_halfsweep": (ctypes.c_int, [_LP, ctypes.c_int32, ctypes.c_int32, _VP]),
     "su2_plaquette": (ctypes.c_int, [_LP, _VP, _VP]),
+    "su2_plaquette_noalloc": (ctypes.c_int, [_LP, _VP, _VP]),
     "su2_polyakov": (ctypes.c_int, [_LP, _VP, _VP, _VP]),
     "su2_measure": (ctypes.c_int, [_LP, _VP, _VP, _VP, _VP]),
     "su2_heatbath_sweep_measured": (ctypes.c_int, [_LP, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, _VP,
@@ -222,6 +223,15 @@ def su2_plaquette(lat, out=None, stream=None):
         out = torch.empty(7, dtype=torch.float64, device=lat.device)
     _tensor(out, lat, torch.float64, 7, "out")
     _check(lib.su2_plaquette(_on_gpu(lat).ref(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def su2_plaquette_noalloc(lat, out, stream=None):
+    """su2_plaquette with the library's static scratch in place of the
+    lattice's workspace: `out` (7 float64 on the lattice's device) must be
+    given, nothing is allocated.  Returns out."""
+    _tensor(out, lat, torch.float64, 7, "out")
+    _check(lib.su2_plaquette_noalloc(_on_gpu(lat).ref(), out.data_ptr(), _stream(stream)))
     return out
 
 

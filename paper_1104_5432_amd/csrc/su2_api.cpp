@@ -52,8 +52,9 @@ uint64_t links_bytes_of(const int32_t n[4], int32_t prec)
     return vol * 4u * (prec == SU2_F32 ? 16u : 32u);
 }
 
-// Common checks of a lattice descriptor.
-int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayout *wl)
+// Checks of a lattice descriptor's extents, precision, id, walk and links;
+// fills *out (without a workspace).
+int check_lattice_links(const su2_lattice_t *lat, su2::LaunchArgs *out)
 {
     if (!lat)
         return fail(SU2_EINVAL, "lattice descriptor is NULL");
@@ -67,19 +68,10 @@ int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayou
         return fail(SU2_EINVAL, "a positive tile (strip width) must divide Nz");
     if (lat->tile_y < 0 || (lat->tile_y > 0 && (lat->tile_y > lat->n[1] || lat->n[1] % lat->tile_y != 0)))
         return fail(SU2_EINVAL, "tile_y must be 0 or a divisor of Ny");
-    if (!lat->links || !lat->work)
-        return fail(SU2_EINVAL, "links and work must be non-NULL device pointers");
-    if (!aligned(lat->links, 16) || !aligned(lat->work, 16))
-        return fail(SU2_EALIGN, "links and work must be 16-byte aligned");
-    const su2::WorkLayout w = su2::work_layout(lat->n);
-    if (lat->work_bytes < w.total)
-        return fail(SU2_EWORK, "work_bytes is smaller than su2_workspace_bytes()");
-    {
-        const uintptr_t l0 = (uintptr_t)lat->links, l1 = l0 + links_bytes_of(lat->n, lat->prec);
-        const uintptr_t w0 = (uintptr_t)lat->work, w1 = w0 + w.total;
-        if (l0 < w1 && w0 < l1)
-            return fail(SU2_EINVAL, "links and work must not overlap");
-    }
+    if (!lat->links)
+        return fail(SU2_EINVAL, "links must be a non-NULL device pointer");
+    if (!aligned(lat->links, 16))
+        return fail(SU2_EALIGN, "links must be 16-byte aligned");
     out->n[0] = lat->n[0];
     out->n[1] = lat->n[1];
     out->n[2] = lat->n[2];
@@ -90,6 +82,30 @@ int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayou
     out->tile_y = lat->tile_y;
     out->volume = (uint64_t)lat->n[0] * lat->n[1] * lat->n[2] * lat->n[3];
     out->links = lat->links;
+    out->work = nullptr;
+    out->flags = nullptr;
+    return SU2_OK;
+}
+
+// Common checks of a lattice descriptor, its workspace included.
+int check_lattice(const su2_lattice_t *lat, su2::LaunchArgs *out, su2::WorkLayout *wl)
+{
+    int rc = check_lattice_links(lat, out);
+    if (rc)
+        return rc;
+    if (!lat->work)
+        return fail(SU2_EINVAL, "work must be a non-NULL device pointer");
+    if (!aligned(lat->work, 16))
+        return fail(SU2_EALIGN, "work must be 16-byte aligned");
+    const su2::WorkLayout w = su2::work_layout(lat->n);
+    if (lat->work_bytes < w.total)
+        return fail(SU2_EWORK, "work_bytes is smaller than su2_workspace_bytes()");
+    {
+        const uintptr_t l0 = (uintptr_t)lat->links, l1 = l0 + links_bytes_of(lat->n, lat->prec);
+        const uintptr_t w0 = (uintptr_t)lat->work, w1 = w0 + w.total;
+        if (l0 < w1 && w0 < l1)
+            return fail(SU2_EINVAL, "links and work must not overlap");
+    }
     out->work = static_cast<char *>(lat->work);
     out->flags = reinterpret_cast<uint32_t *>(lat->work);
     if (wl)
@@ -197,7 +213,7 @@ WorkLayout work_layout(const int32_t n[4])
     // one block per 256 cb indices: also the grid of an update class
     // (class_blocks), whose blocks write here when a last sweep takes the
     // plaquette, so the two must stay equal
-    w.nblk_plaq = (uint32_t)((vol / 2 + 255) / 256);
+    w.nblk_plaq = su2::plaquette_blocks(vol);
     w.nblk_poly = blocks(vs, 2048);
     w.nblk_corr = blocks(vs, 1024);
     uint64_t off = 256; // flags word
@@ -386,6 +402,27 @@ int su2_plaquette(const su2_lattice_t *lat, double *d_out, void *stream)
     if (!aligned(d_out, 8))
         return fail(SU2_EALIGN, "d_out must be 8-byte aligned");
     su2::launch_plaquette(a, w, d_out, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_plaquette_noalloc(const su2_lattice_t *lat, double *d_out, void *stream)
+{
+    su2::LaunchArgs a;
+    int rc = check_lattice_links(lat, &a); // work and work_bytes are not used
+    if (rc)
+        return rc;
+    if (su2::plaquette_blocks(a.volume) > su2::kNoAllocPlaqBlocks)
+        return fail(SU2_EDIMS, "su2_plaquette_noalloc takes at most 44,739,072 sites per parity "
+                               "(V/2 <= 256 x 174762)");
+    if (!d_out)
+        return fail(SU2_EINVAL, "d_out must be a device pointer to 7 doubles");
+    if (!aligned(d_out, 8))
+        return fail(SU2_EALIGN, "d_out must be 8-byte aligned");
+    const hipError_t e = su2::launch_plaquette_noalloc(a, d_out, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        std::snprintf(g_last_error, sizeof g_last_error, "HIP: %s", hipGetErrorString(e));
+        return SU2_EHIP;
+    }
     return launched();
 }
 

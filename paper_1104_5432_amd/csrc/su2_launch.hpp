@@ -32,6 +32,17 @@ struct LaunchArgs {
 
 WorkLayout work_layout(const int32_t n[4]);
 
+// Blocks of a class update and of the plaquette pass: one per 256 cb indices.
+inline uint32_t plaquette_blocks(uint64_t volume)
+{
+    return (uint32_t)((volume / 2 + 255) / 256);
+}
+
+// The no-allocation plaquette's scratch holds the partials of at most this
+// many blocks (6 planes each, 8 MiB in all): V/2 <= 256 x 174762, which
+// takes in 96^4.
+constexpr uint32_t kNoAllocPlaqBlocks = 174762;
+
 // Separations of the Polyakov correlator taken by one block (one load of a
 // site's L for the group); corr_groups(rmax) groups cover r = 1..rmax.
 constexpr uint32_t kCorrGroup = 8;
@@ -67,6 +78,10 @@ void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st);
 void launch_overrelax(const LaunchArgs &a, int mu, int par, double *plaq_partials, hipStream_t st);
 void launch_plaquette_sum(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
+// The plaquette pass with its partials in the library's static scratch
+// (a.work is not used); the lattice must have at most kNoAllocPlaqBlocks
+// plaquette blocks.  Returns the HIP error of the scratch lookup, if any.
+hipError_t launch_plaquette_noalloc(const LaunchArgs &a, double *d_out, hipStream_t st);
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st);
 // d_corr null: no correlator.
 void launch_polyakov_batch(const void *d_table, int count, int prec, const BatchPolyGrid &grid, double *d_poly,

@@ -6,6 +6,8 @@
 #include "su2_device.hpp"
 #include "su2_launch.hpp"
 
+#include <mutex>
+
 namespace su2 {
 
 template <class T>
@@ -383,25 +385,84 @@ void launch_plaquette_sum(const LaunchArgs &a, const WorkLayout &w, double *d_ou
     launch_plaquette_finish(partials, w.nblk_plaq, 1.0 / (double)a.volume, d_out, st);
 }
 
-void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
+// The plaquette pass with its block partials (6 planes x nblk) in `partials`.
+static void launch_plaquette_into(const LaunchArgs &a, uint32_t nblk, double *partials, double *d_out,
+                                  hipStream_t st)
 {
     // The lattice's strip width, but whole columns: with row ranges the
     // plaquette kernel (two sites per thread) fetched 1.5x more.
     const Geom g = make_geom(a.n, a.tile, 1);
-    double *partials = reinterpret_cast<double *>(a.work + w.off_plaq);
     const bool col = col_addressing_ok(g);
     if (a.prec == kF32) {
         if (col)
-            plaquette_kernel<float, true><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
+            plaquette_kernel<float, true><<<nblk, kBlock, 0, st>>>(links_of<float>(a), g, partials);
         else
-            plaquette_kernel<float, false><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<float>(a), g, partials);
+            plaquette_kernel<float, false><<<nblk, kBlock, 0, st>>>(links_of<float>(a), g, partials);
     } else {
         if (col)
-            plaquette_kernel<double, true><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
+            plaquette_kernel<double, true><<<nblk, kBlock, 0, st>>>(links_of<double>(a), g, partials);
         else
-            plaquette_kernel<double, false><<<w.nblk_plaq, kBlock, 0, st>>>(links_of<double>(a), g, partials);
+            plaquette_kernel<double, false><<<nblk, kBlock, 0, st>>>(links_of<double>(a), g, partials);
     }
-    launch_plaquette_finish(partials, w.nblk_plaq, 1.0 / (double)a.volume, d_out, st);
+    launch_plaquette_finish(partials, nblk, 1.0 / (double)a.volume, d_out, st);
+}
+
+void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st)
+{
+    launch_plaquette_into(a, w.nblk_plaq, reinterpret_cast<double *>(a.work + w.off_plaq), d_out, st);
+}
+
+// ---------------------------------------------------------------------------
+// The plaquette without a caller's workspace: the block partials go to a
+// file-scope device array instead.  Each GPU holds its own copy of the array
+// (8 MiB, for as long as the process lives); its address on a device comes
+// from hipGetSymbolAddress, once per device, and is the only form in which
+// host code hands the array to a kernel.  Every call on one GPU overwrites
+// the same array (each block writes its own partials before the finishing
+// kernel reads them, so nothing needs clearing between calls), hence calls
+// that overlap in time on one GPU race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[6u * kNoAllocPlaqBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_lock;
+double *g_scratch_addr[kMaxDevices] = {};
+} // namespace
+
+// Address of the scratch array on the current device (looked up on the
+// first call per device).  Returns hipSuccess or the HIP error.
+static hipError_t scratch_on_current_device(double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> hold(g_scratch_lock);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_addr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_plaquette_noalloc(const LaunchArgs &a, double *d_out, hipStream_t st)
+{
+    const uint32_t nblk = plaquette_blocks(a.volume);
+    if (nblk > kNoAllocPlaqBlocks)
+        return hipErrorInvalidValue; // the caller checked the size first
+    double *partials = nullptr;
+    const hipError_t e = scratch_on_current_device(&partials);
+    if (e != hipSuccess)
+        return e;
+    launch_plaquette_into(a, nblk, partials, d_out, st);
+    return hipSuccess;
 }
 
 void launch_polyakov(const LaunchArgs &a, const WorkLayout &w, double *d_out, double *d_corr, hipStream_t st)

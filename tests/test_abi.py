@@ -103,6 +103,15 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     assert L.su2_overrelax_measured(ok, 1, 0x30004, s) == su2.SU2_EALIGN
     assert L.su2_overrelax_measured(ok, -1, 0x30000, s) == su2.SU2_EINVAL
     assert L.su2_overrelax_measured(by(_desc(su2, wb=need - 1)), 1, 0x30000, s) == su2.SU2_EWORK
+    # the plaquette without a workspace: work may be NULL; size limit, d_out
+    nowork = by(_desc(su2, work=0, wb=0))
+    assert L.su2_plaquette_noalloc(None, 0x30000, s) == su2.SU2_EINVAL
+    assert L.su2_plaquette_noalloc(nowork, None, s) == su2.SU2_EINVAL
+    assert L.su2_plaquette_noalloc(nowork, 0x30004, s) == su2.SU2_EALIGN
+    assert L.su2_plaquette_noalloc(by(_desc(su2, links=0x10000008, work=0, wb=0)), 0x30000, s) == su2.SU2_EALIGN
+    assert L.su2_plaquette_noalloc(by(_desc(su2, n=(128, 128, 128, 128), work=0, wb=0)), 0x30000, s) == \
+        su2.SU2_EDIMS
+    assert L.su2_plaquette_noalloc(by(_desc(su2, n=(8, 7, 8, 8), work=0, wb=0)), 0x30000, s) == su2.SU2_EDIMS
     assert L.su2_get_flags(ok, None, s) == su2.SU2_EINVAL
     assert L.su2_get_flags(ok, 0x30002, s) == su2.SU2_EALIGN
     # tile: a positive strip width must divide Nz
