@@ -69,7 +69,7 @@ def parse():
     return ap.parse_args()
 
 
-SWEEP_SOURCES = ("su2_device.hpp", "su2_kernels.hip", "su2_launch.hpp")
+SWEEP_SOURCES = ("su2_device.hpp", "su2_kernels.hip", "su2_launch.hpp", "su2_staged.hip", "su2_staged.hpp")
 
 
 def csrc_sha256():
@@ -433,17 +433,22 @@ def paper_workload(args):
 def precision_workload(args):
     """FP32 against FP64 links on the benchmarked lattice: for beta 2.3, 2.5
     and 6.0 an FP64 and an FP32 chain (hot start, args.steps steps of 1 heat
-    bath + args.or_per_hb overrelaxation sweeps) and the difference of their
-    mean plaquette and mean |L| in units of the combined Gamma-method error,
-    after discarding the first 20% of sweeps."""
+    bath + args.or_per_hb overrelaxation sweeps), and for every observable the
+    plaquette and the Polyakov-loop calls return -- the mean plaquette and its
+    six planes, the signed mean L, |mean L|, the mean of |L(x)| and the
+    correlator C(r) at every r -- the difference of the two chains' means in
+    units of the combined Gamma-method error, after discarding the first 20%
+    of the steps."""
     import torch
     import paper_1104_5432_amd as su2
     from paper_1104_5432_amd.stats import gamma_method
 
     n = tuple(int(v) for v in args.shape.split(","))
+    rmax = min(n[:3]) // 2
     dev = torch.device("cuda:0")
     rows = {}
     t0 = time.perf_counter()
+    planes = ("01", "02", "03", "12", "13", "23")
     for beta in (2.3, 2.5, 6.0):
         res = {}
         for prec in ("f64", "f32"):
@@ -451,26 +456,42 @@ def precision_workload(args):
             su2.su2_init_hot(lat, args.seed)
             plaq = torch.empty((args.steps, 7), dtype=torch.float64, device=dev)
             poly = torch.empty((args.steps, 2), dtype=torch.float64, device=dev)
+            corr = torch.empty((args.steps, rmax), dtype=torch.float64, device=dev)
             for s in range(args.steps):
                 su2.su2_heatbath_sweep(lat, beta, args.seed, s)
                 su2.su2_overrelax(lat, args.or_per_hb)
                 su2.su2_plaquette(lat, plaq[s])
-                su2.su2_polyakov(lat, poly[s], with_corr=False)
+                su2.su2_polyakov(lat, poly[s], corr[s])
             torch.cuda.synchronize()
             cut = args.steps // 5
-            res[prec] = {"plaquette": gamma_method(plaq[cut:, 0].cpu().numpy())[:2],
-                         "abs_polyakov": gamma_method(np.abs(poly[cut:, 0].cpu().numpy()))[:2],
-                         "flags": int(su2.su2_get_flags(lat).item())}
+            P, L, C = (t[cut:].cpu().numpy() for t in (plaq, poly, corr))
+            series = {"plaquette": P[:, 0], "polyakov": L[:, 0], "abs_polyakov": np.abs(L[:, 0]),
+                      "mean_abs_L": L[:, 1]}
+            for j, name in enumerate(planes):
+                series["plane_" + name] = P[:, 1 + j]
+            for r in range(1, rmax + 1):
+                series[f"corr_r{r}"] = C[:, r - 1]
+            res[prec] = {k: gamma_method(v)[:2] for k, v in series.items()}
+            res[prec]["flags"] = int(su2.su2_get_flags(lat).item())
             del lat
         row = {}
-        for obs in ("plaquette", "abs_polyakov"):
+        for obs in res["f64"]:
+            if obs == "flags":
+                continue
             (m64, e64), (m32, e32) = res["f64"][obs], res["f32"][obs]
+            err = float(np.hypot(e64, e32))
             row[obs] = {"f64": m64, "f64_err": e64, "f32": m32, "f32_err": e32, "diff": m32 - m64,
-                        "z": (m32 - m64) / float(np.hypot(e64, e32))}
+                        "z": (m32 - m64) / err if err > 0 else 0.0}
         row["flags"] = res["f64"]["flags"] | res["f32"]["flags"]
         rows[str(beta)] = row
-        print(f"beta {beta}: {row}", file=sys.stderr, flush=True)
-    zmax = max(abs(r[o]["z"]) for r in rows.values() for o in ("plaquette", "abs_polyakov"))
+        zs = {k: v["z"] for k, v in row.items() if k != "flags"}
+        worst = max(zs, key=lambda k: abs(zs[k]))
+        print(f"beta {beta}: {len(zs)} observables, max |z| {abs(zs[worst]):.2f} ({worst}); "
+              f"plaquette diff {row['plaquette']['diff']:+.2e} z {row['plaquette']['z']:+.2f}; "
+              f"|L| diff {row['abs_polyakov']['diff']:+.2e} z {row['abs_polyakov']['z']:+.2f}; "
+              f"flags {row['flags']}", file=sys.stderr, flush=True)
+    zmax = max(abs(v["z"]) for r in rows.values() for k, v in r.items() if k != "flags")
+    nobs = sum(1 for r in rows.values() for k in r if k != "flags")
     rec = {
         "metric": "FP32 - FP64 observable difference (max |z| over beta and observables)",
         "value": zmax,
@@ -487,8 +508,11 @@ def precision_workload(args):
         "config": {
             "workload": f"SU(2) {'x'.join(map(str, n))}, hot start (Philox seed {args.seed}), FP32 and FP64 "
                         f"chains of {args.steps} steps of 1 heat-bath + {args.or_per_hb} overrelaxation sweeps "
-                        "at beta 2.3, 2.5, 6.0; mean plaquette and mean |L|, Gamma-method errors",
+                        "at beta 2.3, 2.5, 6.0; every observable of the plaquette and Polyakov-loop calls "
+                        "(mean plaquette, six planes, signed mean L, |mean L|, mean |L(x)|, C(r) for every r), "
+                        "Gamma-method errors",
             "lattice": list(n),
+            "observables_compared": nobs,
         },
         "by_beta": rows,
     }

@@ -82,8 +82,13 @@ typedef struct su2_lattice {
     int32_t tile;        /* order in which the threads of a class walk the
                             lattice (performance only, results do not depend
                             on it): 0 = default, W > 0 = (z,t) columns in
-                            z-strips of width W (W must divide Nz), < 0 =
-                            plain checkerboard-index order */
+                            z-strips of width W (W must divide Nz), -1 =
+                            plain checkerboard-index order, -2 = staged:
+                            overrelaxation classes walk slabs whose staple
+                            neighbourhood each block holds in LDS (where a
+                            slab plan fits the lattice and the device's LDS;
+                            not in a sweep that takes the plaquette), the
+                            other kernels the default strips */
     int32_t tile_y;      /* in strip order (tile >= 0): the update kernels
                             walk each column as tile_y ranges of Ny/tile_y
                             rows (tile_y must divide Ny; 0 = default);

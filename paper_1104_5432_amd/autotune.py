@@ -2,11 +2,12 @@
 descriptor) per lattice shape and precision by timing the library's own
 update kernels.
 
-Candidates are plain checkerboard order (tile -1) and every z-strip width W
+Candidates are plain checkerboard order (tile -1), every z-strip width W
 that divides Nz, each with the columns split into S = 1, 2, 4 or 8 row
-ranges (S dividing Ny).  Each candidate runs one heat-bath sweep plus one overrelaxation
-sweep on a scratch lattice (hot start, never the caller's lattice) after a
-warm-up, timed with HIP events on the current stream; the fastest total
+ranges (S dividing Ny), and the LDS-staged overrelaxation (tile -2) with
+the other kernels' default strips in S row ranges.  Each candidate runs one
+heat-bath sweep plus one overrelaxation sweep on a scratch lattice (hot
+start, never the caller's lattice) after a warm-up, timed with HIP events on the current stream; the fastest total
 wins.  The walk changes no result, only the order in which blocks visit the
 lattice, so tuning is safe to apply to any chain.  Choices are cached in a
 JSON file keyed by device architecture, CU count, extents and precision; a
@@ -29,7 +30,9 @@ SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_walks.
 
 
 def candidates(n):
-    """(tile, tile_y) pairs: plain order, then strip widths x row splits."""
+    """(tile, tile_y) pairs: plain order, then strip widths x row splits,
+    then the LDS-staged overrelaxation (tile -2) with the heat bath's
+    default strips split into row ranges."""
     ny, nz = int(n[1]), int(n[2])
     out = [(-1, 0)]
     for w in range(1, nz + 1):
@@ -38,6 +41,9 @@ def candidates(n):
         for sy in (1, 2, 4, 8):
             if ny % sy == 0:
                 out.append((w, sy))
+    for sy in (1, 2, 4, 8):
+        if ny % sy == 0:
+            out.append((-2, sy))
     return out
 
 

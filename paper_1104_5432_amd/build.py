@@ -2,7 +2,8 @@
 
 hipcc compiles every source as HIP for gfx950 only.  Packed-FP32 instruction
 selection is switched off (-packed-fp32-ops): the kernels are written with
-scalar float arithmetic and must not be lowered to v_pk_*_f32.
+scalar float arithmetic and must not be lowered to v_pk_*_f32.  Floating-point
+contraction is limited to single expressions (-ffp-contract=on).
 """
 import os
 import subprocess
@@ -14,11 +15,15 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsu2.so")
-SOURCES = ["su2_kernels.hip", "su2_observables.hip", "su2_learned.hip", "su2_api.cpp"]
+SOURCES = ["su2_kernels.hip", "su2_staged.hip", "su2_observables.hip", "su2_learned.hip", "su2_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # multiply-adds are fused only within one source expression, so every
+    # kernel that forms a quantity with the same expressions rounds it the
+    # same way (the staged and global-memory update kernels agree bitwise)
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-I" + INCLUDE, "-I" + CSRC,
 ]

@@ -262,7 +262,8 @@ __host__ inline BlockOrder make_block_order(const int32_t n[4], int tile, int ti
     o.nz = (uint32_t)n[2];
     o.div_cols = make_fastdiv(o.cols);
     o.div_nt = make_fastdiv((uint32_t)n[3]);
-    const int w = tile == 0 ? default_strip(n) : tile;
+    // tile -2 (staged overrelaxation): the other kernels walk the default strips
+    const int w = (tile == 0 || tile == -2) ? default_strip(n) : tile;
     o.strip = w > 0 ? (uint32_t)w : 0u;
     o.div_w = make_fastdiv(w > 0 ? (uint32_t)w : 1u);
     // row ranges per column: tile_y > 0 as given (it divides Ny; the caller
@@ -737,6 +738,28 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const A &ad, int pa
     return staple_impl<T, MU, false>(U, ad, par, nullptr);
 }
 
+// Overrelaxation of one link from its staple V: U -> Vhat^+ U^+ Vhat^+
+// (FP32 links renormalised).  Returns false, leaving `un` unset, when the
+// link is kept (V = 0, or V not finite: then the flag is raised).  Every
+// overrelaxation kernel forms the new link here.
+template <class T>
+__device__ __forceinline__ bool overrelax_reflect(const Quat<T> &V, const Quat<T> &u, uint32_t *flags, Quat<T> &un)
+{
+    const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
+    const T k = sqrt(k2);
+    if (!isfinite(k)) {
+        atomicOr(flags, kFlagNonFinite);
+        return false;
+    }
+    if (k == T(0))
+        return false;
+    const T inv = T(1) / k;
+    const Quat<T> Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
+    const Quat<T> w = qmul(qmul(Vh, u), Vh);
+    un = unitize(Quat<T>{w.w, -w.x, -w.y, -w.z});
+    return true;
+}
+
 // (1/2) Tr(U W) for unit quaternions: the scalar part of the product.
 template <class T>
 __device__ __forceinline__ T half_trace(const Quat<T> &u, const Quat<T> &w)
@@ -768,8 +791,19 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, cons
 // FP64 5%; 96^4: 3%).  For small lattices, and the batched kernel over many
 // of them, the cap costs more latency hiding than it saves (a batch of
 // 0.1-2 M-site lattices: 10% slower), so it applies from 2^21 links per
-// class.  The cap is an LDS reservation: 36 KB per block, 4 blocks in 160 KB.
-constexpr int kOrResidencyLds = 36 * 1024;
+// class.  The cap is a static LDS reservation the kernel never touches:
+// kOrBlocksPerCu blocks of it fit the CU's kLdsPerCu bytes (gfx950: 160 KB),
+// one more does not.  (Requested as dynamic LDS of the same size at launch,
+// it held the kernel lower than 4 blocks per CU: FP64 class 556 us against
+// 487 us.)  The launcher checks once per device, with the occupancy query,
+// that the capped kernel runs exactly kOrBlocksPerCu blocks per CU, and
+// launches the uncapped one where it does not.
+constexpr int kOrBlocksPerCu = 4;
+constexpr int kLdsPerCu = 160 * 1024;
+constexpr int kOrResidencyLds = kLdsPerCu / kOrBlocksPerCu - 4 * 1024;
+static_assert(kOrBlocksPerCu * kOrResidencyLds <= kLdsPerCu &&
+                  (kOrBlocksPerCu + 1) * kOrResidencyLds > kLdsPerCu,
+              "the reservation must admit exactly kOrBlocksPerCu blocks per CU");
 
 __host__ inline bool residency_cap_pays(const Geom &g)
 {

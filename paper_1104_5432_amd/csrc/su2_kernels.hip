@@ -7,6 +7,7 @@
 #include "su2_launch.hpp"
 
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 namespace su2 {
@@ -334,18 +335,9 @@ __device__ __forceinline__ Quat<T> overrelax_link(const Links<T> &U, const A &ad
     const Quat<T> V = staple_impl<T, MU, PLAQ>(U, ad, par, terms);
     if constexpr (!std::is_same<T, float>::value)
         u = ad.ld_nt(U, MU, par, own);
-    const T k2 = V.w * V.w + V.x * V.x + V.y * V.y + V.z * V.z;
-    const T k = sqrt(k2);
-    if (!isfinite(k)) {
-        atomicOr(flags, kFlagNonFinite);
+    Quat<T> un;
+    if (!overrelax_reflect(V, u, flags, un))
         return u;
-    }
-    if (k == T(0))
-        return u;
-    const T inv = T(1) / k;
-    const Quat<T> Vh = {V.w * inv, V.x * inv, V.y * inv, V.z * inv};
-    const Quat<T> w = qmul(qmul(Vh, u), Vh);
-    const Quat<T> un = unitize(Quat<T>{w.w, -w.x, -w.y, -w.z});
     ad.st(U, MU, par, own, un);
     return un;
 }
@@ -580,6 +572,27 @@ static void launch_hb(const LaunchArgs &a, const Geom &g, int mu, int par, doubl
         launch_hb_mode<T, false, false>(U, g, mu, par, beta, k0, k1, c1, sweep, d_sweep, a.flags, nullptr, st);
 }
 
+// Whether the capped overrelaxation kernel runs exactly kOrBlocksPerCu
+// blocks per CU on the current device (occupancy query, once per device).
+template <class T>
+static bool or_cap_holds()
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex lock;
+    static int cached[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return false;
+    std::lock_guard<std::mutex> hold(lock);
+    if (cached[dev] == 0) {
+        int blocks = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &blocks, overrelax_kernel<T, 0, true, true, false>, kBlock, 0);
+        cached[dev] = (e == hipSuccess && blocks == kOrBlocksPerCu) ? 1 : -1;
+    }
+    return cached[dev] > 0;
+}
+
 template <class T, bool COL, bool CAP, bool PLAQ>
 static void launch_or_mode(const Links<T> &U, const Geom &g, int mu, int par, uint32_t *flags, double *pp,
                            hipStream_t st)
@@ -607,7 +620,7 @@ template <class T>
 static void launch_or(const LaunchArgs &a, const Geom &g, int mu, int par, double *plaq_partials, hipStream_t st)
 {
     const Links<T> U = links_of<T>(a);
-    const bool cap = residency_cap_pays(g);
+    const bool cap = residency_cap_pays(g) && or_cap_holds<T>();
     if (col_addressing_ok(g)) {
         if (cap)
             launch_or_cap<T, true, true>(U, g, mu, par, a.flags, plaq_partials, st);
@@ -645,6 +658,9 @@ void launch_heatbath(const LaunchArgs &a, double beta, uint64_t seed, uint32_t s
 
 void launch_overrelax(const LaunchArgs &a, int mu, int par, double *plaq_partials, hipStream_t st)
 {
+    // the staged kernel takes no plaquette; a class it cannot plan runs here
+    if (a.tile == kTileStaged && !plaq_partials && launch_overrelax_staged(a, mu, par, st))
+        return;
     const Geom g = make_geom(a.n, a.tile, a.tile_y);
     if (a.prec == kF32)
         launch_or<float>(a, g, mu, par, plaq_partials, st);

@@ -14,9 +14,11 @@ Tolerances:
   (different, fixed summation orders).
 - FP32 links: every heat-bath class against the oracle's single-precision
   step from the same configuration (the accept/reject decisions taken in
-  the same precisions): at most one link per class may decide differently,
-  every other link agrees to 2e-6; overrelaxation classes against the FP64
-  oracle on the same FP32 configuration to 2e-6 (no decisions).
+  the same precisions): at most one link per class may decide differently
+  (move by more than 1e-4), every other link agrees to 1e-5 and all but
+  1e-5 of them to 2e-6 (the FP32 staple's rounding, amplified by 1/|V|);
+  overrelaxation classes against the FP64 oracle on the same FP32
+  configuration to the same bounds, with no decision.
 - Ensembles (FP32 vs FP64 chains): means within 3 sigma (Gamma-method
   errors), 2-sigma excursions reported.
 """
@@ -66,13 +68,38 @@ def _flags(su2, lat):
     return int(f.item())
 
 
+# FP32 links against an oracle step on the same FP32 configuration.  The
+# two sides round the FP32 staple differently (FMA contraction, order of the
+# four-term sums), by a few ulp of its six unit terms, i.e. relative to the
+# staple by ~6e-7/|V|; the new link inherits that through Vhat.  Almost every
+# link therefore agrees to 2e-6, but the rare ill-conditioned staples of a
+# hot start (|V| ~ 0.1) let a few links in 10^7 reach ~5e-6 (64^4: 33 of
+# 8.4 million between 2e-6 and 4.4e-6).  A different accept/reject decision
+# is of another kind: the link then comes from another attempt and moves by
+# O(0.1-1).  So: a decision differs where a link moves by more than 1e-4,
+# which at most one link per class may; every other link agrees to 1e-5, and
+# all but 1 + 1e-5 N of the N links to 2e-6.
+FP32_FLIP = 1e-4
+
+
+def _fp32_link_agreement(d, what):
+    flips = int(np.sum(d > FP32_FLIP))
+    rest = np.where(d > FP32_FLIP, 0.0, d)
+    worst = float(rest.max())
+    tail = int(np.sum(rest > 2e-6))
+    print(f"  {what}: {flips} decision(s) differ; other links max |dU| {worst:.2e}, "
+          f"{tail} of {d.size} above 2e-6", flush=True)
+    assert worst <= 1e-5 and tail <= 1 + 1e-5 * d.size, (what, worst, tail)
+    return flips
+
+
 def _fp32_class_against_single_precision_oracle(su2, lat, n, beta, seed, sweep, mu, par):
     """One FP32 heat-bath class on the GPU against the oracle's
-    single-precision step from the same configuration: at most one link may
-    take a different accept/reject decision (a test landing within the
-    last-ulp differences of the two sides' FP32 staples and logarithms), every
-    other link agrees to 2e-6 (FP32 rounding of staple, direction and
-    product), and every link is a unit quaternion.  Returns the GPU's links."""
+    single-precision step from the same configuration (decisions taken in the
+    same precisions): at most one link may decide differently (a test within
+    the rounding differences of the two sides' staples and logarithms), the
+    others agree as above, and every link is a unit quaternion.  Returns the
+    GPU's links."""
     ref = su2.to_canonical(lat).numpy()
     assert oracle.heatbath_halfsweep_f32(n, ref, beta, seed, sweep, mu, par) == 0
     su2.su2_heatbath_halfsweep(lat, beta, seed, sweep, mu, par)
@@ -80,9 +107,7 @@ def _fp32_class_against_single_precision_oracle(su2, lat, n, beta, seed, sweep, 
     got = su2.to_canonical(lat).numpy()
     d = np.max(np.abs(got - ref), axis=-1)
     del ref
-    flips = int(np.sum(d > 2e-6))
-    print(f"  class ({mu},{par}) beta {beta}: {flips} decision(s) differ, "
-          f"max |dU| of the others {float(np.max(np.where(d > 2e-6, 0, d))):.2e}", flush=True)
+    flips = _fp32_link_agreement(d, f"heat-bath class ({mu},{par}) beta {beta}")
     assert flips <= 1, (mu, par, np.sort(d.ravel())[-3:])
     del d
     assert np.max(np.abs((got * got).sum(-1) - 1.0)) <= 6e-7
@@ -91,15 +116,15 @@ def _fp32_class_against_single_precision_oracle(su2, lat, n, beta, seed, sweep, 
 
 def _fp32_or_class_against_oracle(su2, lat, n, mu, par, start):
     """One FP32 overrelaxation class against the FP64 oracle's on the same
-    FP32 configuration: deterministic, so 2e-6 per link."""
+    FP32 configuration: deterministic (no decisions), rounding as above."""
     ref = start.copy()
     oracle.overrelax_halfsweep(n, ref, mu, par)
     su2.su2_overrelax_halfsweep(lat, mu, par)
     _sync()
     got = su2.to_canonical(lat).numpy()
-    err = _maxdiff(got, ref)
+    d = np.max(np.abs(got - ref), axis=-1)
     del ref
-    assert err <= 2e-6, (mu, par, err)
+    assert _fp32_link_agreement(d, f"overrelaxation class ({mu},{par})") == 0
     return got
 
 

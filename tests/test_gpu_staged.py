@@ -1,0 +1,79 @@
+"""The LDS-staged overrelaxation (walk tile = -2) against the global-memory
+kernel: the staple is formed from the LDS copies with the same products and
+sums in the same order, so every class must give bitwise the same links,
+in both precisions, on small lattices (slabs with wrapped halos, several
+slice chunks) and on the benchmarked 64^4."""
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def su2():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1104_5432_amd as m
+    return m
+
+
+def _pair(su2, n, prec, seed):
+    staged = su2.Lattice(n, prec, device="cuda", tile=-2)
+    plain = su2.Lattice(n, prec, device="cuda")
+    su2.su2_init_hot(plain, seed)
+    su2.su2_heatbath_sweep(plain, 2.3, seed, 0)
+    staged.links.copy_(plain.links)
+    return staged, plain
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("n", [(32, 16, 8, 4), (16, 8, 8, 16), (16, 16, 16, 16), (32, 8, 16, 8)])
+def test_staged_overrelax_bitwise(su2, n, prec):
+    print(f"staged overrelaxation {n} {prec}", flush=True)
+    staged, plain = _pair(su2, n, prec, 11)
+    for mu in range(4):
+        for par in range(2):
+            su2.su2_overrelax_halfsweep(staged, mu, par)
+            su2.su2_overrelax_halfsweep(plain, mu, par)
+            torch.cuda.synchronize()
+            assert torch.equal(staged.links, plain.links), (mu, par)
+    su2.su2_overrelax(staged, 2)
+    su2.su2_overrelax(plain, 2)
+    # a last sweep that takes the plaquette (its classes 1-3 odd run the
+    # global-memory kernel)
+    m_s = su2.su2_overrelax_measured(staged, 1)
+    m_p = su2.su2_overrelax_measured(plain, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(staged.links, plain.links)
+    assert torch.equal(m_s, m_p)
+    f = su2.su2_get_flags(staged)
+    torch.cuda.synchronize()
+    assert int(f.item()) == 0
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_staged_overrelax_bitwise_64(su2, prec):
+    n = (64, 64, 64, 64)
+    print(f"staged overrelaxation {n} {prec}", flush=True)
+    staged, plain = _pair(su2, n, prec, 1234)
+    su2.su2_overrelax(staged, 1)
+    su2.su2_overrelax(plain, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(staged.links, plain.links)
+
+
+def test_staged_overrelax_matches_oracle(su2):
+    # and against the oracle directly, FP64, one sweep
+    n = (16, 8, 8, 16)
+    U0 = oracle.init_hot(n, 5)
+    oracle.heatbath_sweep(n, U0, 2.3, 5, 0)
+    lat = su2.Lattice(n, "f64", device="cuda", tile=-2)
+    su2.from_canonical(lat, U0)
+    oracle.overrelax_sweep(n, U0)
+    su2.su2_overrelax(lat, 1)
+    torch.cuda.synchronize()
+    import numpy as np
+    assert float(np.max(np.abs(su2.to_canonical(lat).numpy() - U0))) <= 1e-13

@@ -29,3 +29,18 @@ def test_index_arithmetic_on_host(tmp_path):
                    check=True, capture_output=True)
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "PASSED" in r.stdout, r.stdout[-2000:]
+
+
+def test_staged_index_arithmetic_on_host(tmp_path):
+    # the LDS-staged overrelaxation: every staple link a slab reads from LDS
+    # is the link its loads put there, for every plan the chooser can pick
+    if not (os.path.exists(HIPCC) or shutil.which("hipcc")):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "staged_check")
+    subprocess.run([HIPCC, "-x", "hip", "--offload-host-only", "-O2", "-std=c++17",
+                    "-I" + os.path.join(ROOT, "include"),
+                    "-I" + os.path.join(ROOT, "paper_1104_5432_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "native", "staged_check.cpp"), "-o", exe],
+                   check=True, capture_output=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and "PASSED" in r.stdout, r.stdout[-2000:]
