@@ -45,16 +45,22 @@ __device__ __forceinline__ void stage_direct(const Links<T> &U, const Geom &g, c
     }
 }
 
-// The staple of the site x = xs, slab-relative (a, b), slice sl, parity
-// par, from the LDS copies: the products and sums of staple_impl, in its
-// order.
+// The staple of the site at slab-relative (a, b) of slice sl, parity par,
+// from the LDS copies: the products and sums of staple_impl, in its order.
+// rowbase[k] = staple_row_base(k, a, b) of the thread's site; xhv[0..2] the
+// checkerboard x of the site displaced by -1, 0, +1 in x.  Everything else
+// in an element's index is uniform over the block (scalar).
 template <class T, int MU>
 __device__ __forceinline__ Quat<T> staged_staple(const StagePlan &p, const LdsLink<T> *lds, int32_t s0, int32_t sl,
-                                                 uint32_t nx, uint32_t xs, int32_t a, int32_t b, int par)
+                                                 const uint32_t (&rowbase)[4], const uint32_t (&xhv)[3], int par)
 {
     using R = Roles<MU>;
+    using Ar = Arrays<MU>;
     auto link = [&](int d, int32_t ex, int32_t ea, int32_t eb, int32_t es) -> Quat<T> {
-        return from_lds(lds[staged_link_index<MU>(p, s0, sl, nx, xs, a, b, par, d, ex, ea, eb, es)]);
+        const int k = Ar::array_of(d);
+        const int q = par ^ ((ex + ea + eb + es) & 1);
+        const uint32_t off = staple_shift(p, k, staple_slotq<MU>(k, sl + es, s0, q), ea, eb);
+        return from_lds(lds[rowbase[k] + off + xhv[ex + 1]]);
     };
     constexpr int32_t mx = R::slot(MU) == 0, ma = R::slot(MU) == 1, mb = R::slot(MU) == 2, ms = R::slot(MU) == 3;
     Quat<T> V = {0, 0, 0, 0};
@@ -109,48 +115,65 @@ __global__ __launch_bounds__(kStagedThreads) void overrelax_staged_kernel(Links<
     const bool active = threadIdx.x < sites;
     const uint32_t xh = threadIdx.x % p.nxh, row = threadIdx.x / p.nxh;
     const int32_t a = (int32_t)(row % p.A), b = (int32_t)(row / p.A);
-    const uint32_t yc = y0 + (uint32_t)a, bc = b0 + (uint32_t)b;
+    const uint32_t yb = y0 + (uint32_t)a + b0 + (uint32_t)b; // y + b of the site
+    const uint32_t own_cb0 = xh + p.nxh * global_row_base<MU>(g, y0, b0, a, b);
+    uint32_t rowbase[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        rowbase[k] = staple_row_base<MU>(p, k, a, b);
 
-    // a slice's share in registers (arrays 0-2 of slice sl, array 3 of
-    // sl + 1) and the thread's own link of slice sl, loaded one slice ahead
+    // the thread's share of each slice's loads (arrays 0-2 of slice sl,
+    // array 3 of sl + 1), decoded once; the next slice's share and own link
+    // are held in registers
     constexpr int kPre = staged_prefetch(sizeof(T) * 4);
+    LoadBase lb[kPre];
+#pragma unroll
+    for (int r = 0; r < kPre; ++r) {
+        const uint32_t i = threadIdx.x + (uint32_t)r * kStagedThreads;
+        if (!(i < p.n_fresh && load_base<MU>(g, p, y0, b0, opp, i, lb[r])))
+            lb[r].info = 0xffffffffu;
+    }
     Quat<T> pre[kPre];
-    uint32_t pre_lds[kPre];
     Quat<T> pre_own = {1, 0, 0, 0};
     auto prefetch = [&](int32_t sl) {
+        const SliceTerms t = slice_terms<MU>(g, p, s0, sl);
         if (active)
-            pre_own = U.ld_nt(MU, par, xh + p.nxh * global_row<MU>(g, y0, b0, a, b, sl));
+            pre_own = U.ld_nt(MU, par, own_cb0 + t.cb_s);
 #pragma unroll
         for (int r = 0; r < kPre; ++r) {
-            const uint32_t i = threadIdx.x + (uint32_t)r * kStagedThreads;
-            LoadItem it;
-            pre_lds[r] = 0xffffffffu;
-            if (i < p.n_fresh && load_item<MU>(g, p, y0, b0, s0, 15u, sl, sl + 1, opp, i, it)) {
-                pre[r] = U.ld(it.dir, it.parity, it.cb);
-                pre_lds[r] = it.lds;
+            if (lb[r].info != 0xffffffffu) {
+                uint32_t cb, li;
+                load_at(lb[r], t, cb, li);
+                const int plane = (int)(lb[r].info & 0xffu);
+                pre[r] = U.ld(plane >> 1, plane & 1, cb);
             }
         }
     };
     prefetch(s0);
 
     for (int32_t sl = s0; sl < s0 + (int32_t)p.S; ++sl) {
+        const SliceTerms t = slice_terms<MU>(g, p, s0, sl);
 #pragma unroll
-        for (int r = 0; r < kPre; ++r)
-            if (pre_lds[r] != 0xffffffffu)
-                lds[pre_lds[r]] = {pre[r].w, pre[r].x, pre[r].y, pre[r].z};
+        for (int r = 0; r < kPre; ++r) {
+            if (lb[r].info != 0xffffffffu) {
+                uint32_t cb, li;
+                load_at(lb[r], t, cb, li);
+                lds[li] = {pre[r].w, pre[r].x, pre[r].y, pre[r].z};
+            }
+        }
         const Quat<T> own = pre_own;
         __syncthreads();
         if (sl + 1 < s0 + (int32_t)p.S)
             prefetch(sl + 1);
         if (active) {
-            const uint32_t own_cb = xh + p.nxh * global_row<MU>(g, y0, b0, a, b, sl);
-            // x of the site from its row's parity offset
+            // x of the site from its row's parity offset, and its neighbours'
             const uint32_t sc = (uint32_t)(sl < nsl ? sl : sl - nsl);
-            const uint32_t xs = 2u * xh + ((yc + bc + sc + (uint32_t)par) & 1u);
-            const Quat<T> V = staged_staple<T, MU>(p, lds, s0, sl, nx, xs, a, b, par);
+            const uint32_t xs = 2u * xh + ((yb + sc + (uint32_t)par) & 1u);
+            const uint32_t xhv[3] = {shifted_xh(xs, -1, nx), xh, shifted_xh(xs, 1, nx)};
+            const Quat<T> V = staged_staple<T, MU>(p, lds, s0, sl, rowbase, xhv, par);
             Quat<T> un;
             if (overrelax_reflect(V, own, flags, un))
-                U.st(MU, par, own_cb, un);
+                U.st(MU, par, own_cb0 + t.cb_s, un);
         }
         __syncthreads();
     }

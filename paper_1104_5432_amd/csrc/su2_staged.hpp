@@ -140,19 +140,35 @@ __host__ __device__ inline uint32_t lds_index(const ArrayShape &sh, uint32_t nxh
 }
 
 // Global row index y + Ny (z + Nz t) of slab-relative (a, b) in slice sl,
-// every coordinate wrapped into the lattice.
+// every coordinate wrapped into the lattice, as the sum of a part without
+// the marched coordinate (global_row_base) and that coordinate's term
+// (slice_row).
 template <int MU>
-__host__ __device__ inline uint32_t global_row(const Geom &g, uint32_t y0, uint32_t b0, int32_t a, int32_t b,
-                                               int32_t sl)
+__host__ __device__ inline uint32_t global_row_base(const Geom &g, uint32_t y0, uint32_t b0, int32_t a, int32_t b)
 {
-    const int32_t ny = g.n[1], nb = g.n[Roles<MU>::b], ns = g.n[Roles<MU>::s];
+    const int32_t ny = g.n[1], nb = g.n[Roles<MU>::b];
     int32_t y = (int32_t)y0 + a;
     y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
     int32_t bb = (int32_t)b0 + b;
     bb = bb < 0 ? bb + nb : (bb >= nb ? bb - nb : bb);
+    // b is z (mu != t: row term Ny z) or t (mu = t: row term Ny Nz t)
+    return (uint32_t)y + (uint32_t)g.n[1] * (uint32_t)bb * (MU == 3 ? (uint32_t)g.n[2] : 1u);
+}
+
+template <int MU>
+__host__ __device__ inline uint32_t slice_row(const Geom &g, int32_t sl)
+{
+    const int32_t ns = g.n[Roles<MU>::s];
     const int32_t ss = sl < 0 ? sl + ns : (sl >= ns ? sl - ns : sl);
-    const uint32_t z = (uint32_t)(MU == 3 ? ss : bb), t = (uint32_t)(MU == 3 ? bb : ss);
-    return (uint32_t)y + (uint32_t)g.n[1] * (z + (uint32_t)g.n[2] * t);
+    // s is t (mu != t: row term Ny Nz t) or z (mu = t: row term Ny z)
+    return (uint32_t)g.n[1] * (uint32_t)ss * (MU == 3 ? 1u : (uint32_t)g.n[2]);
+}
+
+template <int MU>
+__host__ __device__ inline uint32_t global_row(const Geom &g, uint32_t y0, uint32_t b0, int32_t a, int32_t b,
+                                               int32_t sl)
+{
+    return global_row_base<MU>(g, y0, b0, a, b) + slice_row<MU>(g, sl);
 }
 
 // The i-th link a slab loads of the arrays in `which` (bit k = array k):
@@ -210,6 +226,104 @@ __host__ __device__ inline uint32_t load_count(const StagePlan &p, uint32_t whic
     return n;
 }
 
+// A load item of the slice loop split into what does not depend on the
+// slice (computed once per block and thread) and the per-slice terms: the
+// kernel forms each slice's checkerboard index and LDS element by two
+// additions (load_at).  The same split as load_item, which the host test
+// checks.
+struct LoadBase {
+    uint32_t cb0;  // checkerboard index without the marched coordinate's term
+    uint32_t lds0; // LDS element in ring slot 0
+    uint32_t info; // plane 2 dir + parity | array << 8
+};
+
+template <int MU>
+__host__ __device__ inline bool load_base(const Geom &g, const StagePlan &p, uint32_t y0, uint32_t b0, int opp,
+                                          uint32_t i, LoadBase &lb)
+{
+    using Ar = Arrays<MU>;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const ArrayShape &sh = p.arr[k];
+        const uint32_t per_par = sh.rows * p.nxh;
+        const uint32_t n = per_par * (uint32_t)Ar::parities(k);
+        if (i >= n) {
+            i -= n;
+            continue;
+        }
+        const uint32_t q = Ar::parities(k) == 1 ? 0u : fdiv(i, p.div_pp[k]);
+        const uint32_t rem = i - q * per_par;
+        const uint32_t row = fdiv(rem, p.div_nxh);
+        const uint32_t xh = rem - row * p.nxh;
+        const uint32_t bb = fdiv(row, p.div_ra[k]);
+        const int32_t a = (int32_t)(row - bb * sh.ra) - (int32_t)sh.lo_a;
+        const int32_t b = (int32_t)bb - (int32_t)sh.lo_b;
+        const int parity = k == 3 ? opp : (int)q;
+        lb.cb0 = xh + p.nxh * global_row_base<MU>(g, y0, b0, a, b);
+        lb.lds0 = lds_index(sh, p.nxh, q, a, b, xh);
+        lb.info = (uint32_t)(2 * Ar::dir(k) + parity) | ((uint32_t)k << 8);
+        return true;
+    }
+    return false;
+}
+
+// The per-slice terms of arrays 0-2 at slice sl and of array 3 at sl + 1.
+struct SliceTerms {
+    uint32_t cb_s, cb_m;   // checkerboard-index terms of the marched coordinate
+    uint32_t lds_0, lds_3; // ring-slot offsets of arrays 0 and 3
+};
+
+template <int MU>
+__host__ __device__ inline SliceTerms slice_terms(const Geom &g, const StagePlan &p, int32_t s0, int32_t sl)
+{
+    using Ar = Arrays<MU>;
+    SliceTerms t;
+    t.cb_s = p.nxh * slice_row<MU>(g, sl);
+    t.cb_m = p.nxh * slice_row<MU>(g, sl + 1);
+    t.lds_0 = ring_slot(sl, s0, Ar::slots(0)) * (uint32_t)Ar::parities(0) * p.arr[0].rows * p.nxh;
+    t.lds_3 = ring_slot(sl + 1, s0, Ar::slots(3)) * (uint32_t)Ar::parities(3) * p.arr[3].rows * p.nxh;
+    return t;
+}
+
+__host__ __device__ inline void load_at(const LoadBase &lb, const SliceTerms &t, uint32_t &cb, uint32_t &lds)
+{
+    const uint32_t k = lb.info >> 8;
+    cb = lb.cb0 + (k == 3 ? t.cb_m : t.cb_s);
+    lds = lb.lds0 + (k == 0 ? t.lds_0 : (k == 3 ? t.lds_3 : 0u));
+}
+
+// LDS element of a staple link as the sum of a per-thread row base of its
+// array (fixed for a block's thread), a uniform offset of the displacement
+// and ring slot, and the displaced x position (staged_link_index).
+template <int MU>
+__host__ __device__ inline uint32_t staple_row_base(const StagePlan &p, int k, int32_t a, int32_t b)
+{
+    const ArrayShape &sh = p.arr[k];
+    return sh.base + ((uint32_t)(a + (int32_t)sh.lo_a) + sh.ra * (uint32_t)(b + (int32_t)sh.lo_b)) * p.nxh;
+}
+
+__host__ __device__ inline uint32_t staple_shift(const StagePlan &p, int k, uint32_t slotq, int32_t ea, int32_t eb)
+{
+    const ArrayShape &sh = p.arr[k];
+    return slotq * sh.rows * p.nxh + (uint32_t)((ea + (int32_t)sh.ra * eb) * (int32_t)p.nxh);
+}
+
+// checkerboard x position of x = xs displaced by ex in {-1, 0, 1}
+__host__ __device__ inline uint32_t shifted_xh(uint32_t xs, int32_t ex, uint32_t nx)
+{
+    int32_t xx = (int32_t)xs + ex;
+    xx = xx < 0 ? xx + (int32_t)nx : (xx >= (int32_t)nx ? xx - (int32_t)nx : xx);
+    return (uint32_t)xx >> 1;
+}
+
+// ring and parity slot of a staple link of array k (parity of its site q)
+template <int MU>
+__host__ __device__ inline uint32_t staple_slotq(int k, int32_t sl, int32_t s0, int q)
+{
+    using Ar = Arrays<MU>;
+    return ring_slot(sl, s0, Ar::slots(k)) * (uint32_t)Ar::parities(k) + (k == 3 ? 0u : (uint32_t)q);
+}
+
 // LDS element of the direction-d link at the site displaced by (ex, ea, eb,
 // es) (in x, y, b, s) from the site at x = xs, slab-relative (a, b), slice
 // sl, of parity par.
@@ -218,14 +332,10 @@ __host__ __device__ inline uint32_t staged_link_index(const StagePlan &p, int32_
                                                       uint32_t xs, int32_t a, int32_t b, int par, int d, int32_t ex,
                                                       int32_t ea, int32_t eb, int32_t es)
 {
-    using Ar = Arrays<MU>;
-    int32_t xx = (int32_t)xs + ex;
-    xx = xx < 0 ? xx + (int32_t)nx : (xx >= (int32_t)nx ? xx - (int32_t)nx : xx);
+    const int k = Arrays<MU>::array_of(d);
     const int q = par ^ ((ex + ea + eb + es) & 1);
-    const int k = Ar::array_of(d);
-    const ArrayShape &sh = p.arr[k];
-    const uint32_t slotq = ring_slot(sl + es, s0, Ar::slots(k)) * (uint32_t)Ar::parities(k) + (k == 3 ? 0u : (uint32_t)q);
-    return lds_index(sh, p.nxh, slotq, a + ea, b + eb, (uint32_t)xx >> 1);
+    return staple_row_base<MU>(p, k, a, b) + staple_shift(p, k, staple_slotq<MU>(k, sl + es, s0, q), ea, eb) +
+           shifted_xh(xs, ex, nx);
 }
 
 // Host: a slab plan for class MU of lattice n, or false if none fits in

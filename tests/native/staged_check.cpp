@@ -86,7 +86,23 @@ static void check_plan(const int32_t n[4], const StagePlan &p, int par)
         stage(1u, s0 - 1, 0);
         stage(8u, 0, s0 - 1);
         stage(8u, 0, s0);
+        // the slice loop's loads as the kernel forms them: decoded once
+        // (load_base), then per slice (load_at); they must be load_item's
+        std::vector<LoadBase> bases(p.n_fresh);
+        for (uint32_t i = 0; i < p.n_fresh; ++i)
+            if (!load_base<MU>(g, p, y0, b0, opp, i, bases[i]))
+                fail("load_base range", MU, n, p, (long)i);
         for (int32_t sl = s0; sl < s0 + (int32_t)p.S; ++sl) {
+            const SliceTerms terms = slice_terms<MU>(g, p, s0, sl);
+            for (uint32_t i = 0; i < p.n_fresh; ++i) {
+                LoadItem it;
+                load_item<MU>(g, p, y0, b0, s0, 15u, sl, sl + 1, opp, i, it);
+                uint32_t cb, li;
+                load_at(bases[i], terms, cb, li);
+                const int plane = (int)(bases[i].info & 0xffu);
+                if (cb != it.cb || li != it.lds || plane != 2 * it.dir + it.parity)
+                    fail("load_base/load_at differ from load_item", MU, n, p, (long)i);
+            }
             stage(15u, sl, sl + 1);
             for (uint32_t u = 0; u < sites; ++u) {
                 const uint32_t xh = u % p.nxh, row = u / p.nxh;
