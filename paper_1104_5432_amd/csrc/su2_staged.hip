@@ -1,9 +1,10 @@
 // su2_staged.hip -- overrelaxation with the staple neighbourhood of a slab
 // staged in LDS (the slab plan and index arithmetic are in su2_staged.hpp).
 // A block walks its slab slice by slice; for each slice it writes the
-// links it loaded during the previous slice into LDS, issues the next
-// slice's loads (its share of the neighbourhood and each thread's own link)
-// into registers and then forms every staple of the slice from LDS.  Each link of the class's neighbourhood is read from
+// links it loaded two slices earlier (one in FP64) into LDS, issues the
+// loads of the slice after next (its share of the neighbourhood and each
+// thread's own link) into registers and then forms every staple of the
+// slice from LDS.  Each link of the class's neighbourhood is read from
 // memory once per slab (the halo rows once more by the neighbouring slab)
 // in contiguous 128-bit accesses along x: ~10 loads per update instead of
 // 19.  The staple is formed with the products and sums of staple_impl, in
@@ -133,38 +134,50 @@ __global__ __launch_bounds__(kStagedThreads) void overrelax_staged_kernel(Links<
         if (!(i < p.n_fresh && load_base<MU>(g, p, y0, b0, opp, i, lb[r])))
             lb[r].info = 0xffffffffu;
     }
-    Quat<T> pre[kPre];
-    Quat<T> pre_own = {1, 0, 0, 0};
-    auto prefetch = [&](int32_t sl) {
+    // Two register buffers, so that a slice's loads are issued two slices
+    // before the slice is written to LDS (FP32; FP64 keeps one, its links
+    // taking twice the registers).
+    constexpr int kDepth = sizeof(T) == 4 ? 2 : 1;
+    Quat<T> pre[kDepth][kPre];
+    Quat<T> pre_own[kDepth];
+    auto prefetch = [&](int32_t sl, Quat<T>(&buf)[kPre], Quat<T> &own_out) {
         const SliceTerms t = slice_terms<MU>(g, p, s0, sl);
         if (active)
-            pre_own = U.ld_nt(MU, par, own_cb0 + t.cb_s);
+            own_out = U.ld_nt(MU, par, own_cb0 + t.cb_s);
 #pragma unroll
         for (int r = 0; r < kPre; ++r) {
             if (lb[r].info != 0xffffffffu) {
                 uint32_t cb, li;
                 load_at(lb[r], t, cb, li);
                 const int plane = (int)(lb[r].info & 0xffu);
-                pre[r] = U.ld(plane >> 1, plane & 1, cb);
+                buf[r] = U.ld(plane >> 1, plane & 1, cb);
             }
         }
     };
-    prefetch(s0);
+    const int32_t s_end = s0 + (int32_t)p.S;
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+        pre_own[d] = {1, 0, 0, 0};
+        if (s0 + d < s_end)
+            prefetch(s0 + d, pre[d], pre_own[d]);
+    }
 
-    for (int32_t sl = s0; sl < s0 + (int32_t)p.S; ++sl) {
+    // slice sl from buffer d: write its share to LDS, issue the loads of
+    // slice sl + kDepth into the same buffer, update the slice
+    auto slice = [&](int32_t sl, int d) {
         const SliceTerms t = slice_terms<MU>(g, p, s0, sl);
 #pragma unroll
         for (int r = 0; r < kPre; ++r) {
             if (lb[r].info != 0xffffffffu) {
                 uint32_t cb, li;
                 load_at(lb[r], t, cb, li);
-                lds[li] = {pre[r].w, pre[r].x, pre[r].y, pre[r].z};
+                lds[li] = {pre[d][r].w, pre[d][r].x, pre[d][r].y, pre[d][r].z};
             }
         }
-        const Quat<T> own = pre_own;
+        const Quat<T> own = pre_own[d];
         __syncthreads();
-        if (sl + 1 < s0 + (int32_t)p.S)
-            prefetch(sl + 1);
+        if (sl + kDepth < s_end)
+            prefetch(sl + kDepth, pre[d], pre_own[d]);
         if (active) {
             // x of the site from its row's parity offset, and its neighbours'
             const uint32_t sc = (uint32_t)(sl < nsl ? sl : sl - nsl);
@@ -176,6 +189,12 @@ __global__ __launch_bounds__(kStagedThreads) void overrelax_staged_kernel(Links<
                 U.st(MU, par, own_cb0 + t.cb_s, un);
         }
         __syncthreads();
+    };
+    for (int32_t sl = s0; sl < s_end; sl += kDepth) {
+#pragma unroll
+        for (int d = 0; d < kDepth; ++d)
+            if (sl + d < s_end)
+                slice(sl + d, d);
     }
 }
 
