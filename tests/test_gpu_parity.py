@@ -538,7 +538,8 @@ def test_observables_gauge_invariant_on_gpu(su2):
 # ---------------------------------------------------------------------------
 # full size (64^4), the configuration the benchmark times
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("prec,beta", [("f32", 2.3), ("f64", 2.3), ("f64", 2.5), ("f64", 6.0)])
+@pytest.mark.parametrize("prec,beta", [("f32", 2.3), ("f32", 2.5), ("f32", 6.0), ("f64", 2.3), ("f64", 2.5),
+                                       ("f64", 6.0)])
 def test_full_size_64(su2, prec, beta):
     n, seed = (64, 64, 64, 64), 1234
     print(f"full-size parity {n} {prec} beta {beta}", flush=True)
