@@ -1,7 +1,13 @@
-"""Statistics used by the statistical pins and the FP32-versus-FP64 checks.
+"""Statistics used by the statistical pins and the FP32-versus-FP64 checks
+(test infrastructure: nothing here comes from the package under test).
 
-- gamma_method: re-exported from paper_1104_5432_amd.stats (Wolff's Gamma
-  method), pinned in tests/test_stats.py.
+- blocking_error: the error of the mean of an autocorrelated series by
+  blocking (Flyvbjerg and Petersen, J. Chem. Phys. 91 (1989) 461): block
+  means over blocks of 2^l samples, the standard error of the mean at every
+  level that still has at least 32 blocks, and the largest of them (the
+  plateau for a series much longer than its autocorrelation time).  A
+  different method from the package's Gamma method, written separately;
+  pinned in tests/test_stats.py by the closed form for an AR(1) process.
 - x0_cdf: the exact conditional distribution function of w0 = (1/2)Tr(W)
   when W has density ~ exp(alpha w0) with respect to Haar measure on SU(2),
   i.e. w0 has density ~ sqrt(1 - w0^2) exp(alpha w0) on [-1, 1].  Computed
@@ -14,7 +20,25 @@ import numpy as np
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(96)
 
 
-from paper_1104_5432_amd.stats import gamma_method  # noqa: E402,F401  (pinned in test_stats.py)
+def blocking_error(a, min_blocks=32):
+    """Return (mean, error, tau_int, levels) of the series a by blocking;
+    tau_int = (error / naive error)^2 / 2, levels = the blocking levels used."""
+    a = np.asarray(a, dtype=np.float64)
+    mean = float(a.mean())
+    n = a.size
+    if n < 2:
+        return mean, 0.0, 0.5, 0
+    naive = float(a.std(ddof=1) / np.sqrt(n))
+    x = a.copy()
+    err = naive
+    level = 0
+    while x.size >= 2 * min_blocks:
+        m = x.size // 2
+        x = 0.5 * (x[:2 * m:2] + x[1:2 * m:2])
+        level += 1
+        err = max(err, float(x.std(ddof=1) / np.sqrt(x.size)))
+    tau = 0.5 * (err / naive) ** 2 if naive > 0 else 0.5
+    return mean, err, tau, level
 
 
 def _x0_unnormalised(alpha, w):

@@ -174,8 +174,8 @@ def test_learned_chain_is_exact(su2):
         b = np.array(res["learned"][key][200:])
         if key == "polyakov":
             a, b = np.abs(a), np.abs(b)
-        ma, ea, _, _ = stats_util.gamma_method(a)
-        mb, eb, _, _ = stats_util.gamma_method(b)
+        ma, ea, _, _ = stats_util.blocking_error(a)
+        mb, eb, _, _ = stats_util.blocking_error(b)
         z = (mb - ma) / np.hypot(ea, eb)
         print(f"{key}: hb {ma:.5f}({ea:.5f}) learned {mb:.5f}({eb:.5f}) z = {z:+.2f}", flush=True)
         assert abs(z) <= 3.0

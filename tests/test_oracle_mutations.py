@@ -102,10 +102,9 @@ CASES = ([m + ("test_oracle_pins.py",) for m in MUTATIONS]
 
 @pytest.mark.slow
 @pytest.mark.parametrize("name,old,new,pins", CASES, ids=[c[0] for c in CASES])
-def test_pins_catch_planted_mistake(name, old, new, pins):
-    tree = os.path.join(HERE, "_build", "mutant")
-    if os.path.exists(tree):
-        shutil.rmtree(tree)
+def test_pins_catch_planted_mistake(name, old, new, pins, tmp_path):
+    # a tree of its own per case, so that cases can run in parallel workers
+    tree = str(tmp_path / "mutant")
     os.makedirs(tree)
     ign = shutil.ignore_patterns("*.so", "__pycache__", "_build")
     shutil.copytree(os.path.join(ROOT, "oracle"), os.path.join(tree, "oracle"), ignore=ign)
@@ -121,8 +120,8 @@ def test_pins_catch_planted_mistake(name, old, new, pins):
     b = subprocess.run([sys.executable, os.path.join("oracle", "build.py")], cwd=tree, capture_output=True,
                        text=True, timeout=300)
     assert b.returncode == 0, f"mutant does not build: {name}\n{b.stderr[-2000:]}"
-    # the copy's oracle and tests come first on the path; the statistics
-    # helpers the tests share with the package resolve to this repository
+    # the copy's oracle and tests come first on the path (the working
+    # directory); anything else resolves to this repository
     env = dict(os.environ, PYTHONPATH=ROOT)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join("tests", pins) + "::" + CATCHES[name]],
