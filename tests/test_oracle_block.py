@@ -4,6 +4,9 @@ Hastings step on the marginal of a block centre).
 - Bessel functions against scipy.special.ive (a separate implementation).
 - The block piece identity |V_o(T)|^2 = |S_o|^2 + 1 + 2 (1/2)Tr(T S_o)
   against the oracle's staple function with T written into the lattice.
+- The proposal's coefficients: c_o is the slope of the o-th factor of the
+  log marginal at (1/2)Tr(T S_o) = 0 (central difference of scipy's
+  Bessel function), times exp(y_o); the directions add.
 - The action decomposition behind the marginal: changing a block centre and
   its six neighbours changes the brute-force Wilson action by exactly
   -beta sum_o d[(1/2)Tr(T_o V_o(T_e))].
@@ -58,6 +61,42 @@ def test_block_piece_identity():
             lhs = float(V @ V)
             rhs = float(S @ S) + 1 + 2 * oracle.qmul(T, S)[0]
             assert abs(lhs - rhs) <= 1e-12, (d, lhs, rhs)
+
+
+def test_block_proposal_is_the_slope_of_the_marginal():
+    # The proposal's effective staple M = sum_o c_o S_o takes for c_o (at
+    # y_o = 0) the slope of the o-th factor of the marginal,
+    # log Z(beta sqrt(|S_o|^2 + 1 + 2w)) in w = (1/2)Tr(T S_o), at w = 0,
+    # times exp(y_o).  Each direction is isolated by giving the others
+    # y = -60 (weight e^-60); the slope comes from a central difference of
+    # scipy's Bessel function, not from the oracle's.
+    n, beta = (8, 8, 8, 2), 2.3
+    U = oracle.init_hot(n, 21)
+    rng = np.random.default_rng(8)
+    h = 1e-5
+    for _ in range(6):
+        x, y, z, t = [int(v) for v in rng.integers(0, 8, 3)] + [int(rng.integers(0, 2))]
+        e = _site(n, x, y, z, t)
+        S = [oracle.block_piece(n, U, e, d) for d in range(6)]
+        for d in range(6):
+            s2 = float(S[d] @ S[d])
+
+            def f(w):
+                a = beta * np.sqrt(s2 + 1 + 2 * w)
+                return np.log(2 * special.ive(1, a) / a) + a
+
+            slope = (f(h) - f(-h)) / (2 * h)
+            for yd in (0.0, 0.7, -1.3):
+                y6 = np.full(6, -60.0)
+                y6[d] = yd
+                M = oracle.block_proposal(n, U, e, beta, y6)
+                want = slope * np.exp(yd) * S[d]
+                assert np.allclose(M, want, rtol=1e-7, atol=1e-7 * np.linalg.norm(want)), (d, yd, M, want)
+        # all directions at once: the sum of the isolated ones
+        y6 = rng.normal(scale=0.5, size=6)
+        M = oracle.block_proposal(n, U, e, beta, y6)
+        parts = [oracle.block_proposal(n, U, e, beta, np.where(np.arange(6) == d, y6, -60.0)) for d in range(6)]
+        assert np.allclose(M, np.sum(parts, 0), rtol=1e-12, atol=1e-12)
 
 
 def test_block_action_decomposition():

@@ -52,9 +52,9 @@ MUTATIONS = [
 
 # Mistakes in the learned block move (Metropolis-Hastings on the block
 # marginal, then a heat-bath redraw of the integrated links), caught by its
-# own pins (tests/test_oracle_block.py).  A wrong proposal coefficient is not
-# among them: the move is exact for any proposal, so only its acceptance
-# changes.
+# own pins (tests/test_oracle_block.py).  The move is exact for any proposal,
+# so a wrong proposal coefficient changes only its acceptance; the pin of
+# the coefficients as slopes of the marginal catches it.
 BLOCK_MUTATIONS = [
     ("block move: proposal terms swapped", "half_tr(T, M) - half_tr(Tn, M);", "half_tr(Tn, M) - half_tr(T, M);"),
     ("block move: marginal dropped", "double logr = block_log_marginal(beta, S, Tn) - block_log_marginal(beta, S, T) +",
@@ -63,6 +63,8 @@ BLOCK_MUTATIONS = [
     ("block move: redraw at beta = 1", "double Vb[4] = {beta * V[0], beta * V[1], beta * V[2], beta * V[3]};",
      "double Vb[4] = {V[0], V[1], V[2], V[3]};"),
     ("block move: no redraw", "memcpy(U + (o * 4 + 3) * 4, Un, sizeof Un);", ";"),
+    ("block move: proposal coefficient", "or_bessel_ratio(a0) / sqrt(s * s + 1.0) * exp(y[d])",
+     "or_bessel_ratio(a0) * sqrt(s * s + 1.0) * exp(y[d])"),
 ]
 
 # The pin that catches each mistake (others may catch it too).
@@ -94,6 +96,7 @@ CATCHES = {
     'block move: accept test reversed': 'test_block_move_samples_the_marginal',
     'block move: redraw at beta = 1': 'test_block_move_redraws_the_neighbours_from_their_conditional_law',
     'block move: no redraw': 'test_block_move_redraws_the_neighbours_from_their_conditional_law',
+    'block move: proposal coefficient': 'test_block_proposal_is_the_slope_of_the_marginal',
 }
 
 CASES = ([m + ("test_oracle_pins.py",) for m in MUTATIONS]
