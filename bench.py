@@ -60,6 +60,10 @@ def parse():
                          "paper: the paper's own benchmark (random start, 100 heat-bath iterations at "
                          "beta 6.0 with the mean plaquette each) over lattice sizes, FP32 and FP64, "
                          "against one core of the CPU oracle")
+    ap.add_argument("--persistent", action="store_true",
+                    help="scan: run each sweep's heat bath and overrelaxation of all lattices in one "
+                         "persistent launch (grid-wide barrier between classes) instead of one launch "
+                         "per class")
     ap.add_argument("--fused-plaquette", action=argparse.BooleanOptionalAction, default=True,
                     help="take the plaquette in the last sweep of the step (no separate pass); "
                          "--no-fused-plaquette measures it with the one-pass measurement kernel")
@@ -163,8 +167,11 @@ def scan(args):
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        su2.su2_batch_heatbath_sweep(batch, args.seed, d_sweep=d_sweep)
-        su2.su2_batch_overrelax(batch, args.or_per_hb)
+        if args.persistent:
+            su2.su2_batch_sweep(batch, args.seed, d_sweep=d_sweep, n_or=args.or_per_hb)
+        else:
+            su2.su2_batch_heatbath_sweep(batch, args.seed, d_sweep=d_sweep)
+            su2.su2_batch_overrelax(batch, args.or_per_hb)
         su2.su2_batch_polyakov(batch, poly, corr)
         su2.su2_sweep_advance(d_sweep)
     torch.cuda.synchronize()
@@ -211,8 +218,10 @@ def scan(args):
         "config": {
             "workload": "finite-temperature scan: 16 SU(2) lattices cycling 32^3x4, 48^3x6, 64^3x8, "
                         "beta 2.2..2.7, hot start, per sweep one captured graph: 1 heat-bath + "
-                        f"{args.or_per_hb} overrelaxation sweeps of all lattices + Polyakov loop and "
-                        "correlator of each",
+                        f"{args.or_per_hb} overrelaxation sweeps of all lattices "
+                        + ("in one persistent launch " if args.persistent else "in one launch per class ")
+                        + "+ Polyakov loop and correlator of each",
+            "persistent": bool(args.persistent),
             "lattices": [list(lat.n) for lat in lats],
             "betas": betas,
             "link_updates_per_step": updates,

@@ -47,9 +47,10 @@
  *    SU2_EHIP reports a failed launch; su2_last_error() then holds the HIP
  *    message (thread-local).
  *  - Device-side anomalies set sticky bits in a flags word in the workspace:
- *    SU2_FLAG_CAP (a sampler hit its attempt cap; the link was kept) and
- *    SU2_FLAG_NONFINITE (a staple was not finite; the link was kept).  Both
- *    starts clear it; su2_get_flags() copies it out.
+ *    SU2_FLAG_CAP (a sampler hit its attempt cap; the link was kept),
+ *    SU2_FLAG_NONFINITE (a staple was not finite; the link was kept) and
+ *    SU2_FLAG_SYNC (su2_batch_sweep: a barrier wait gave up).  Both starts
+ *    clear it; su2_get_flags() copies it out.
  */
 #ifndef SU2_H
 #define SU2_H
@@ -73,6 +74,7 @@ enum {
 
 #define SU2_FLAG_CAP 1u
 #define SU2_FLAG_NONFINITE 2u
+#define SU2_FLAG_SYNC 4u /* su2_batch_sweep: a grid-wide barrier wait gave up */
 #define SU2_MAX_ATTEMPTS 4096
 
 typedef struct su2_lattice {
@@ -228,6 +230,27 @@ int su2_batch_heatbath_sweep(const su2_lattice_t *lats, int32_t count, const voi
 /* n_sweeps overrelaxation sweeps of every lattice of the batch. */
 int su2_batch_overrelax(const su2_lattice_t *lats, int32_t count, const void *d_table, int32_t n_sweeps,
                         void *stream);
+
+/* The same as su2_batch_heatbath_sweep followed by su2_batch_overrelax with
+ * n_or sweeps (Sec. 2.1 heat bath, then overrelaxation), bit for bit, in ONE
+ * persistent launch: its grid is at most the blocks the device keeps
+ * resident at once, each block takes the batched launches' blocks in turn,
+ * and all blocks meet at a grid-wide barrier between classes (8 * (1 + n_or)
+ * classes).  d_sync: device, one uint32, 4-byte aligned, the barrier's
+ * counter: its low 31 bits must be 0 before the first call (zero it once)
+ * and every call leaves them 0; bit 31 is the barrier's phase, flipped by
+ * each barrier.  Calls that share a d_sync must not overlap, and nothing else should run
+ * on the device meanwhile: the barrier needs every block of the grid
+ * resident.  A barrier wait gives up after spin_limit polls (0: the default,
+ * a few tenths of a second, against a normal wait of tens of microseconds) and sets
+ * SU2_FLAG_SYNC in every lattice's flags word; the call still ends, with
+ * unreliable links.  The sweep index is *d_sweep if d_sweep is not NULL (so a
+ * captured graph of this one launch and su2_sweep_advance can be replayed),
+ * else sweep.  Errors: those of su2_batch_heatbath_sweep; SU2_EINVAL for n_or
+ * outside [0, 64] or a NULL d_sync; SU2_EALIGN for a misaligned d_sync;
+ * SU2_EHIP if the kernel cannot be resident on the device. */
+int su2_batch_sweep(const su2_lattice_t *lats, int32_t count, const void *d_table, uint64_t seed, uint32_t sweep,
+                    const uint32_t *d_sweep, int32_t n_or, uint32_t *d_sync, uint32_t spin_limit, void *stream);
 
 /* Polyakov loop and on-axis correlator (Sec. 2.2, eqs. (1) and (3)) of every
  * lattice of the batch, each exactly as su2_polyakov computes it (the same

@@ -73,6 +73,8 @@ _SIGNATURES = {
                                                 _VP]),
     "su2_batch_overrelax": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, ctypes.c_int32, _VP]),
     "su2_batch_polyakov": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    "su2_batch_sweep": (ctypes.c_int, [_LP, ctypes.c_int32, _VP, ctypes.c_uint64, ctypes.c_uint32, _VP,
+                                       ctypes.c_int32, _VP, ctypes.c_uint32, _VP]),
     "su2_sweep_advance": (ctypes.c_int, [_VP, _VP]),
     "su2_lp_param_count": (ctypes.c_int32, []),
     "su2_lp_workspace_bytes": (ctypes.c_uint64, [_I4]),
@@ -334,6 +336,9 @@ class Batch:
         self.count = count
         host, self.descs = su2_batch_fill(self.lattices, betas)
         self.table = torch.frombuffer(bytearray(host), dtype=torch.uint8).to(self.lattices[0].device)
+        # the persistent sweep's barrier counter (bits 0-30 zero before and
+        # after every call; bit 31 is the barrier phase)
+        self.sync = torch.zeros(1, dtype=torch.int32, device=self.lattices[0].links.device)
 
 
 def su2_batch_heatbath_sweep(batch, seed, sweep=0, d_sweep=None, stream=None):
@@ -350,6 +355,19 @@ def su2_batch_overrelax(batch, n_sweeps=1, stream=None):
     _batch_on_gpu(batch)
     _check(lib.su2_batch_overrelax(batch.descs, batch.count, batch.table.data_ptr(), int(n_sweeps),
                                    _stream(stream)))
+
+
+def su2_batch_sweep(batch, seed, sweep=0, d_sweep=None, n_or=4, spin_limit=0, stream=None):
+    """One heat-bath sweep and n_or overrelaxation sweeps of every lattice in
+    one persistent launch (bitwise su2_batch_heatbath_sweep followed by
+    su2_batch_overrelax(n_or)); the barrier counter is batch.sync."""
+    _batch_on_gpu(batch)
+    if d_sweep is not None:
+        _tensor(d_sweep, batch.lattices[0], torch.int32, 1, "d_sweep")
+    _tensor(batch.sync, batch.lattices[0], torch.int32, 1, "batch.sync")
+    _check(lib.su2_batch_sweep(batch.descs, batch.count, batch.table.data_ptr(), int(seed), int(sweep),
+                               d_sweep.data_ptr() if d_sweep is not None else None, int(n_or),
+                               batch.sync.data_ptr(), int(spin_limit), _stream(stream)))
 
 
 def su2_batch_polyakov(batch, poly=None, corr=None, with_corr=True, stream=None):

@@ -145,6 +145,12 @@ uint64_t round256(uint64_t b)
 }
 
 constexpr int kMaxBatch = 4096;
+constexpr int kMaxBatchOr = 64; // overrelaxation sweeps of one persistent batched call
+// Polls of a persistent sweep's barrier wait before it gives up: each poll
+// is a device-scope load (about a microsecond) and a short sleep, so a few
+// tenths of a second, against a legitimate wait of one block's work (tens
+// of microseconds).
+constexpr uint32_t kDefaultSpinLimit = 1u << 18;
 
 uint32_t round8(uint32_t b)
 {
@@ -554,6 +560,29 @@ int su2_batch_overrelax(const su2_lattice_t *lats, int32_t count, const void *d_
         for (int mu = 0; mu < 4; ++mu)
             for (int p = 0; p < 2; ++p)
                 su2::launch_overrelax_batch(d_table, count, lats[0].prec, total, mu, p, (hipStream_t)stream);
+    return launched();
+}
+
+int su2_batch_sweep(const su2_lattice_t *lats, int32_t count, const void *d_table, uint64_t seed, uint32_t sweep,
+                    const uint32_t *d_sweep, int32_t n_or, uint32_t *d_sync, uint32_t spin_limit, void *stream)
+{
+    uint32_t total = 0;
+    int rc = check_batch(lats, count, &total);
+    if (rc)
+        return rc;
+    if (!d_table || !aligned(d_table, 8))
+        return fail(SU2_EINVAL, "d_table must be an 8-byte aligned device pointer");
+    if (d_sweep && !aligned(d_sweep, 4))
+        return fail(SU2_EALIGN, "d_sweep must be 4-byte aligned");
+    if (n_or < 0 || n_or > kMaxBatchOr)
+        return fail(SU2_EINVAL, "n_or must be in [0, 64]");
+    if (!d_sync)
+        return fail(SU2_EINVAL, "d_sync must be a device pointer");
+    if (!aligned(d_sync, 4))
+        return fail(SU2_EALIGN, "d_sync must be 4-byte aligned");
+    if (!su2::launch_batch_sweep(d_table, count, lats[0].prec, total, seed, sweep, d_sweep, n_or, d_sync,
+                                 spin_limit ? spin_limit : kDefaultSpinLimit, (hipStream_t)stream))
+        return fail(SU2_EHIP, "the persistent sweep kernel cannot be resident on this device");
     return launched();
 }
 

@@ -11,6 +11,7 @@ namespace su2 {
 constexpr double kPi = 3.14159265358979323846;
 constexpr uint32_t kFlagCap = 1u;
 constexpr uint32_t kFlagNonFinite = 2u;
+constexpr uint32_t kFlagSync = 4u; // a grid-wide barrier wait gave up (persistent batched sweep)
 constexpr uint32_t kMaxAttempts = 4096u;
 constexpr int kBlock = 256; // threads per block of every lattice kernel
 

@@ -173,18 +173,23 @@ __device__ __forceinline__ void plaquette_partials(const Quat<T> &u, const Plane
             partials[(size_t)plane_index(nu, MU) * gridDim.x + blockIdx.x] = acc[nu];
 }
 
+// Block-shared state of the heat bath's compaction of rejected lanes (one
+// per kernel, so that a kernel running several classes holds it once).
+struct HbShared {
+    uint32_t queue[kBlock];
+    uint32_t site[kBlock];
+    double alpha[kBlock];
+    double x0[kBlock];
+    double xlen[kBlock];
+    uint32_t wcount[kBlock / 64];
+};
+
 template <class T, int MU, bool COL, bool PLAQ = false>
 __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, int par, double beta,
                                               uint32_t k0, uint32_t k1, uint32_t c1, uint32_t sweep,
-                                              uint32_t *flags, uint32_t b, uint32_t nblocks,
+                                              uint32_t *flags, uint32_t b, uint32_t nblocks, HbShared &sh,
                                               double *plaq_partials = nullptr)
 {
-    __shared__ uint32_t s_queue[kBlock];
-    __shared__ uint32_t s_site[kBlock];
-    __shared__ double s_alpha[kBlock];
-    __shared__ double s_x0[kBlock];
-    __shared__ double s_xlen[kBlock];
-    __shared__ uint32_t s_wcount[kBlock / 64];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t i = xcd_tile(b, nblocks) * kBlock + tid;
@@ -260,37 +265,37 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     const uint64_t mask = __ballot(retry);
     if (retry) {
         const uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
-        s_queue[wave * 64u + rank] = tid;
-        s_site[tid] = site;
-        s_alpha[tid] = alpha;
+        sh.queue[wave * 64u + rank] = tid;
+        sh.site[tid] = site;
+        sh.alpha[tid] = alpha;
     }
     if (lane == 0)
-        s_wcount[wave] = (uint32_t)__popcll(mask);
+        sh.wcount[wave] = (uint32_t)__popcll(mask);
     __syncthreads();
     uint32_t total = 0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w)
-        total += s_wcount[w];
+        total += sh.wcount[w];
     for (uint32_t qi = tid; qi < total; qi += kBlock) {
         uint32_t w = 0, r = qi;
-        while (r >= s_wcount[w]) {
-            r -= s_wcount[w];
+        while (r >= sh.wcount[w]) {
+            r -= sh.wcount[w];
             ++w;
         }
-        const uint32_t src = s_queue[w * 64u + r];
-        const double a_src = s_alpha[src];
+        const uint32_t src = sh.queue[w * 64u + r];
+        const double a_src = sh.alpha[src];
         const double inv2a_src = 1.0 / (2.0 * fmax(a_src, 1.0));
         double qx0 = 0.0, qxl = -1.0;
         for (uint32_t a = 1; a < kMaxAttempts; ++a)
-            if (sampler_attempt<T>(a_src, inv2a_src, s_site[src], c1, sweep, a, k0, k1, qx0, qxl))
+            if (sampler_attempt<T>(a_src, inv2a_src, sh.site[src], c1, sweep, a, k0, k1, qx0, qxl))
                 break;
-        s_x0[src] = qx0;
-        s_xlen[src] = qxl;
+        sh.x0[src] = qx0;
+        sh.xlen[src] = qxl;
     }
     __syncthreads();
     if (retry) {
-        x0 = s_x0[tid];
-        xlen = s_xlen[tid];
+        x0 = sh.x0[tid];
+        xlen = sh.xlen[tid];
         ok = xlen >= 0.0;
         if (!ok)
             atomicOr(flags, kFlagCap);
@@ -383,8 +388,9 @@ __global__ __launch_bounds__(kBlock) void heatbath_kernel(Links<T> U, Geom g, in
                                                            uint32_t sweep, const uint32_t *d_sweep,
                                                            uint32_t *flags, double *plaq_partials)
 {
+    __shared__ HbShared sh;
     const uint32_t sw = d_sweep ? *d_sweep : sweep;
-    heatbath_body<T, MU, COL, PLAQ>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x,
+    heatbath_body<T, MU, COL, PLAQ>(U, g, par, beta, k0, k1, c1, sw, flags, blockIdx.x, gridDim.x, sh,
                                     plaq_partials);
 }
 
@@ -407,35 +413,132 @@ __device__ __forceinline__ const BatchEntry &find_entry(const BatchEntry *tab, i
     return tab[find_entry_index<&BatchEntry::block0>(tab, count, blockIdx.x)];
 }
 
+// Block `item` of a batched class launch (the lattice's blocks item - block0).
+template <class T, int MU>
+__device__ __forceinline__ void heatbath_item(const BatchEntry &e, int par, uint32_t k0, uint32_t k1, uint32_t sw,
+                                              uint32_t item, HbShared &sh)
+{
+    Links<T> U;
+    U.p = reinterpret_cast<decltype(U.p)>(e.links);
+    U.half = e.g.half;
+    const uint32_t c1 = (uint32_t)MU + 4u * 1u + e.lid16;
+    if (e.col)
+        heatbath_body<T, MU, true>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, item - e.block0, e.nblocks, sh);
+    else
+        heatbath_body<T, MU, false>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, item - e.block0, e.nblocks, sh);
+}
+
+template <class T, int MU>
+__device__ __forceinline__ void overrelax_item(const BatchEntry &e, int par, uint32_t item)
+{
+    Links<T> U;
+    U.p = reinterpret_cast<decltype(U.p)>(e.links);
+    U.half = e.g.half;
+    if (e.col)
+        overrelax_body<T, MU, true>(U, e.g, par, e.flags, item - e.block0, e.nblocks);
+    else
+        overrelax_body<T, MU, false>(U, e.g, par, e.flags, item - e.block0, e.nblocks);
+}
+
 template <class T, int MU>
 __global__ __launch_bounds__(kBlock) void heatbath_batch_kernel(const BatchEntry *tab, int count, int par,
                                                                  uint32_t k0, uint32_t k1, uint32_t sweep,
                                                                  const uint32_t *d_sweep)
 {
-    const BatchEntry &e = find_entry(tab, count);
-    Links<T> U;
-    U.p = reinterpret_cast<decltype(U.p)>(e.links);
-    U.half = e.g.half;
+    __shared__ HbShared sh;
     const uint32_t sw = d_sweep ? *d_sweep : sweep;
-    const uint32_t c1 = (uint32_t)MU + 4u * 1u + e.lid16;
-    if (e.col)
-        heatbath_body<T, MU, true>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, blockIdx.x - e.block0, e.nblocks);
-    else
-        heatbath_body<T, MU, false>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, blockIdx.x - e.block0,
-                                    e.nblocks);
+    heatbath_item<T, MU>(find_entry(tab, count), par, k0, k1, sw, blockIdx.x, sh);
 }
 
 template <class T, int MU>
 __global__ __launch_bounds__(kBlock) void overrelax_batch_kernel(const BatchEntry *tab, int count, int par)
 {
-    const BatchEntry &e = find_entry(tab, count);
-    Links<T> U;
-    U.p = reinterpret_cast<decltype(U.p)>(e.links);
-    U.half = e.g.half;
-    if (e.col)
-        overrelax_body<T, MU, true>(U, e.g, par, e.flags, blockIdx.x - e.block0, e.nblocks);
-    else
-        overrelax_body<T, MU, false>(U, e.g, par, e.flags, blockIdx.x - e.block0, e.nblocks);
+    overrelax_item<T, MU>(find_entry(tab, count), par, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched sweep: one launch runs the eight heat-bath classes and
+// then n_or overrelaxation sweeps (8 classes each) of every lattice of a
+// batch.  The grid holds at most the blocks the device keeps resident at
+// once, a multiple of 8; block b takes the items b, b + G, b + 2G, ... of a
+// class, an item being one block of the batched class launch (the same
+// lattice, walk position and arithmetic, so the same links bit for bit).
+// As G is a multiple of 8, block b (dispatched to XCD b mod 8) only takes
+// items of that XCD's range of each lattice's walk.  Classes are separated
+// by a grid-wide barrier.
+//
+// The barrier counts arrivals in one word: every block adds 1 except block
+// 0, which adds 2^31 - (G - 1), so the G arrivals of a barrier sum to 2^31:
+// bit 31 flips exactly when the last block arrives and bits 0-30 return to
+// 0.  A block waits until bit 31 differs from the value its own addition
+// returned (no barrier can complete again before every block has arrived
+// there, so a late reader cannot miss a flip).  The addition is a release
+// and the wait ends with an acquire, both at device scope, after a block
+// barrier: every store of every block before the barrier is visible to
+// every load after it, across XCDs.  The wait is bounded: after spin_limit
+// polls the block sets kFlagSync in every lattice's flags and goes on, so
+// every block still ends (the links are then unreliable); each block still
+// adds once per barrier, so bits 0-30 of the word end the launch at 0
+// either way (bit 31, the phase, flips once per barrier).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grid_barrier(uint32_t *word, uint32_t spin_limit, const BatchEntry *tab, int count)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t inc = blockIdx.x == 0 ? 0x80000000u - (gridDim.x - 1u) : 1u;
+        const uint32_t old = __hip_atomic_fetch_add(word, inc, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t polls = 0;
+        bool flipped = false;
+        while (!(flipped = (((__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ old) &
+                              0x80000000u) != 0u)) &&
+               ++polls < spin_limit)
+            __builtin_amdgcn_s_sleep(4);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (!flipped)
+            for (int j = 0; j < count; ++j)
+                atomicOr(tab[j].flags, kFlagSync);
+    }
+    __syncthreads();
+}
+
+// The items b, b + G, ... of one class of the persistent sweep.
+template <class T, int MU, bool HB>
+__device__ __forceinline__ void batch_class_items(const BatchEntry *tab, int count, uint32_t total, int par,
+                                                  uint32_t k0, uint32_t k1, uint32_t sw, HbShared &sh)
+{
+    for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const BatchEntry &e = tab[find_entry_index<&BatchEntry::block0>(tab, count, item)];
+        if constexpr (HB)
+            heatbath_item<T, MU>(e, par, k0, k1, sw, item, sh);
+        else
+            overrelax_item<T, MU>(e, par, item);
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void batch_sweep_kernel(const BatchEntry *tab, int count, uint32_t total,
+                                                             uint32_t k0, uint32_t k1, uint32_t sweep,
+                                                             const uint32_t *d_sweep, int n_or, uint32_t *sync,
+                                                             uint32_t spin_limit)
+{
+    __shared__ HbShared sh;
+    const uint32_t sw = d_sweep ? *d_sweep : sweep;
+    const int classes = 8 * (1 + n_or);
+    for (int c = 0; c < classes; ++c) {
+        const int mu = (c & 7) >> 1, par = c & 1;
+        switch ((c < 8 ? 0 : 4) + mu) {
+        case 0: batch_class_items<T, 0, true>(tab, count, total, par, k0, k1, sw, sh); break;
+        case 1: batch_class_items<T, 1, true>(tab, count, total, par, k0, k1, sw, sh); break;
+        case 2: batch_class_items<T, 2, true>(tab, count, total, par, k0, k1, sw, sh); break;
+        case 3: batch_class_items<T, 3, true>(tab, count, total, par, k0, k1, sw, sh); break;
+        case 4: batch_class_items<T, 0, false>(tab, count, total, par, k0, k1, sw, sh); break;
+        case 5: batch_class_items<T, 1, false>(tab, count, total, par, k0, k1, sw, sh); break;
+        case 6: batch_class_items<T, 2, false>(tab, count, total, par, k0, k1, sw, sh); break;
+        default: batch_class_items<T, 3, false>(tab, count, total, par, k0, k1, sw, sh); break;
+        }
+        if (c + 1 < classes)
+            grid_barrier(sync, spin_limit, tab, count);
+    }
 }
 
 __global__ void sweep_advance_kernel(uint32_t *d_sweep)
@@ -712,6 +815,57 @@ void launch_overrelax_batch(const void *d_table, int count, int prec, uint32_t t
         launch_or_batch<float>(tab, count, total_blocks, mu, par, st);
     else
         launch_or_batch<double>(tab, count, total_blocks, mu, par, st);
+}
+
+// Blocks of batch_sweep_kernel<T> the current device holds at once (the
+// occupancy query times the CU count, once per device), rounded down to a
+// multiple of 8; 0 if it cannot be resident.
+template <class T>
+static uint32_t batch_sweep_resident()
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex lock;
+    static int64_t cached[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return 0;
+    std::lock_guard<std::mutex> hold(lock);
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_sweep_kernel<T>, kBlock, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            per_cu = cus = 0;
+        const int64_t n = ((int64_t)per_cu * cus) & ~int64_t(7);
+        cached[dev] = n > 0 ? n : -1;
+    }
+    return cached[dev] > 0 ? (uint32_t)cached[dev] : 0u;
+}
+
+template <class T>
+static bool launch_batch_sweep_t(const BatchEntry *tab, int count, uint32_t total, uint64_t seed, uint32_t sweep,
+                                 const uint32_t *d_sweep, int n_or, uint32_t *d_sync, uint32_t spin_limit,
+                                 hipStream_t st)
+{
+    const uint32_t resident = batch_sweep_resident<T>();
+    if (resident == 0)
+        return false;
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    const uint32_t grid = total < resident ? total : resident; // both multiples of 8
+    batch_sweep_kernel<T><<<dim3(grid), dim3(kBlock), 0, st>>>(tab, count, total, k0, k1, sweep, d_sweep, n_or,
+                                                               d_sync, spin_limit);
+    return true;
+}
+
+bool launch_batch_sweep(const void *d_table, int count, int prec, uint32_t total_blocks, uint64_t seed,
+                        uint32_t sweep, const uint32_t *d_sweep, int n_or, uint32_t *d_sync, uint32_t spin_limit,
+                        hipStream_t st)
+{
+    const BatchEntry *tab = static_cast<const BatchEntry *>(d_table);
+    if (prec == kF32)
+        return launch_batch_sweep_t<float>(tab, count, total_blocks, seed, sweep, d_sweep, n_or, d_sync, spin_limit,
+                                           st);
+    return launch_batch_sweep_t<double>(tab, count, total_blocks, seed, sweep, d_sweep, n_or, d_sync, spin_limit,
+                                        st);
 }
 
 void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st)

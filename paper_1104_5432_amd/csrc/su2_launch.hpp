@@ -74,6 +74,12 @@ void launch_heatbath_batch(const void *d_table, int count, int prec, uint32_t to
                            uint64_t seed, uint32_t sweep, const uint32_t *d_sweep, hipStream_t st);
 void launch_overrelax_batch(const void *d_table, int count, int prec, uint32_t total_blocks, int mu, int par,
                             hipStream_t st);
+// One persistent launch: the heat-bath sweep and n_or overrelaxation sweeps
+// of every lattice of the batch, classes separated by a grid-wide barrier on
+// *d_sync; false (nothing launched) if the kernel cannot be resident.
+bool launch_batch_sweep(const void *d_table, int count, int prec, uint32_t total_blocks, uint64_t seed,
+                        uint32_t sweep, const uint32_t *d_sweep, int n_or, uint32_t *d_sync, uint32_t spin_limit,
+                        hipStream_t st);
 void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st);
 void launch_overrelax(const LaunchArgs &a, int mu, int par, double *plaq_partials, hipStream_t st);
 // Walk value (descriptor field `tile`) of the LDS-staged overrelaxation:

@@ -138,6 +138,7 @@ def test_argument_checks_reject_before_any_hip_call(su2):
         dup = (su2.su2_lattice_t * 2)(d0, other)
         assert L.su2_batch_fill(dup, betas, 2, host, nb) == su2.SU2_EINVAL
         assert L.su2_batch_overrelax(dup, 2, 0x40000, 1, s) == su2.SU2_EINVAL
+        assert L.su2_batch_sweep(dup, 2, 0x40000, 1, 0, None, 4, 0x80000, 0, s) == su2.SU2_EINVAL
     assert L.su2_batch_fill(arr, betas, 2, host, nb - 1) == su2.SU2_EWORK
     assert L.su2_batch_fill(arr, betas, 0, host, nb) == su2.SU2_EINVAL
     assert L.su2_batch_fill(None, betas, 2, host, nb) == su2.SU2_EINVAL
@@ -151,6 +152,18 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     assert L.su2_batch_heatbath_sweep(arr, 2, 0x40004, 1, 0, None, s) == su2.SU2_EINVAL
     assert L.su2_batch_heatbath_sweep(arr, 2, 0x40000, 1, 0, 0x50002, s) == su2.SU2_EALIGN
     assert L.su2_batch_overrelax(arr, 2, 0x40000, -1, s) == su2.SU2_EINVAL
+    # the persistent sweep: table, sweep index, overrelaxation count and
+    # barrier word are checked before anything is launched
+    bs = L.su2_batch_sweep
+    assert bs(arr, 2, None, 1, 0, None, 4, 0x80000, 0, s) == su2.SU2_EINVAL
+    assert bs(arr, 2, 0x40004, 1, 0, None, 4, 0x80000, 0, s) == su2.SU2_EINVAL
+    assert bs(arr, 2, 0x40000, 1, 0, 0x50002, 4, 0x80000, 0, s) == su2.SU2_EALIGN
+    for n_or in (-1, 65):
+        assert bs(arr, 2, 0x40000, 1, 0, None, n_or, 0x80000, 0, s) == su2.SU2_EINVAL
+    assert bs(arr, 2, 0x40000, 1, 0, None, 4, None, 0, s) == su2.SU2_EINVAL
+    assert bs(arr, 2, 0x40000, 1, 0, None, 4, 0x80002, 0, s) == su2.SU2_EALIGN
+    assert bs(mixed, 2, 0x40000, 1, 0, None, 4, 0x80000, 0, s) == su2.SU2_EINVAL
+    assert bs(arr, 0, 0x40000, 1, 0, None, 4, 0x80000, 0, s) == su2.SU2_EINVAL
     rmax = 4                                       # the larger min(Nx,Ny,Nz)/2 of 8^4 and 4^3x6
     assert L.su2_batch_polyakov(arr, 2, None, 0x60000, None, 0, s) == su2.SU2_EINVAL
     assert L.su2_batch_polyakov(arr, 2, 0x40000, None, None, 0, s) == su2.SU2_EINVAL
@@ -194,6 +207,15 @@ def test_layout_conversion_matches_documented_layout(su2, prec):
             d2 = lat.links.view(torch.float64).view(-1, 2)
             v = np.concatenate([d2[(2 * q) * half + cb].numpy(), d2[(2 * q + 1) * half + cb].numpy()])
         assert np.max(np.abs(v - U[t, z, y, x, mu])) <= tol
+
+
+def test_batch_sweep_binding_refuses_host_lattices(su2):
+    lats = [su2.Lattice((8, 8, 8, 4), "f32", device="cpu", lattice_id=0),
+            su2.Lattice((4, 4, 4, 6), "f32", device="cpu", lattice_id=1)]
+    batch = su2.Batch(lats, [2.3, 2.4])
+    assert batch.sync.dtype == __import__("torch").int32 and int(batch.sync.item()) == 0
+    with pytest.raises(ValueError):
+        su2.su2_batch_sweep(batch, 1, n_or=4)
 
 
 def test_batch_polyakov_binding_checks_its_tensors(su2):
