@@ -9,6 +9,14 @@ the on-axis correlator C(r) = <L(x) L(x + r e_i)> -- and turns them into:
   Z(g^2) = exp(A g^2 + B g^4) and g^2 = 4/beta (the SU(2) Wilson action);
   A = 0.0637, B = 0.0731 are the paper's fitted values (stated valid for
   g^2 < 1.3);
+- the procedure that gives Z(g^2) (the paper follows the iterative
+  renormalisation of Gupta, Huebner and Kaczmarek, seeded by zero-
+  temperature static potentials): a seed Z at one coupling from matching
+  the bare free energy at short distance to the renormalised zero-
+  temperature potential (the self energy of the two static charges is the
+  only difference between them there), its transfer to other couplings
+  through lattices of different Nt at the same temperature (where the
+  renormalised loops must agree), and the fit of ln Z = A g^2 + B g^4;
 - the colour-averaged free energy of a static pair, eq. (3): with L
   normalised by 1/2, (1/4)<Tr L Tr L^+> equals C(r), so
   F_avg(r)/T = -ln C(r) + const; the paper's shift F -> F - T ln 4 is
@@ -40,6 +48,62 @@ def renormalization_z(beta, A=PAPER_Z_A, B=PAPER_Z_B):
 def renormalized_polyakov(L, beta, nt, A=PAPER_Z_A, B=PAPER_Z_B):
     """<L^r> = Z(g^2)^Nt <L> (eq. (2)); L may be a mean or an array of means."""
     return renormalization_z(beta, A, B) ** int(nt) * np.asarray(L, dtype=np.float64)
+
+
+def z_from_short_distance(r, corr, nt, v_ren, r_max):
+    """Seed of the renormalisation: ln Z at one coupling from the bare
+    correlator C(r) of a lattice with Nt time slices and the renormalised
+    zero-temperature potential a V(r) (lattice units) at the same coupling.
+
+    With L^r = Z^Nt L the correlator renormalises as C^r = Z^(2 Nt) C, so
+    a F^r(r) = -(1/Nt) ln C^r(r) = a F(r) - 2 ln Z.  At distances well below
+    1/T the free energy is the zero-temperature potential, so over
+    r <= r_max:  ln Z = mean of (a F(r) - a V(r)) / 2.  Returns (ln Z, the
+    spread of the per-r values, which vanishes when the match holds)."""
+    r = np.asarray(r, dtype=np.float64)
+    aF = -np.log(np.asarray(corr, dtype=np.float64)) / float(nt)
+    d = (aF - np.asarray(v_ren, dtype=np.float64)) / 2.0
+    sel = r <= r_max
+    if not np.any(sel):
+        raise ValueError("no separation at or below r_max")
+    return float(d[sel].mean()), float(d[sel].std())
+
+
+def z_transfer(ln_z_ref, loop_ref, nt_ref, loop_new, nt_new):
+    """Carry ln Z from a coupling where it is known to another one through
+    two lattices at the same temperature: (Nt_ref, beta_ref) with bare loop
+    loop_ref and (Nt_new, beta_new) with loop_new.  Equal renormalised loops,
+    Z_ref^Nt_ref L_ref = Z_new^Nt_new L_new (eq. (2)), give
+    ln Z_new = (Nt_ref ln Z_ref + ln L_ref - ln L_new) / Nt_new."""
+    return (nt_ref * ln_z_ref + np.log(loop_ref) - np.log(loop_new)) / float(nt_new)
+
+
+def fit_z(g2, ln_z, d_ln_z=None):
+    """Weighted least squares of ln Z(g^2) = A g^2 + B g^4 (the form the
+    paper fits).  Returns ((A, B), covariance, chi2/dof)."""
+    g2 = np.asarray(g2, dtype=np.float64)
+    y = np.asarray(ln_z, dtype=np.float64)
+    w = np.ones_like(y) if d_ln_z is None else 1.0 / np.asarray(d_ln_z, dtype=np.float64) ** 2
+    X = np.stack([g2, g2 * g2], axis=1)
+    XtW = X.T * w
+    cov = np.linalg.inv(XtW @ X)
+    p = cov @ (XtW @ y)
+    res = y - X @ p
+    chi2 = float((w * res * res).sum()) / max(1, len(y) - 2)
+    return p, cov, chi2
+
+
+def renormalisation_chain(seed, steps):
+    """The iterative procedure: seed = (g2, ln Z) at the starting coupling;
+    steps = [(g2_ref, g2_new, loop_ref, nt_ref, loop_new, nt_new), ...], each
+    a pair of lattices at one temperature whose reference coupling already
+    has ln Z (the seed or an earlier step).  Returns {g2: ln Z}."""
+    known = {float(seed[0]): float(seed[1])}
+    for g2_ref, g2_new, loop_ref, nt_ref, loop_new, nt_new in steps:
+        if float(g2_ref) not in known:
+            raise ValueError(f"no ln Z yet at g^2 = {g2_ref}")
+        known[float(g2_new)] = float(z_transfer(known[float(g2_ref)], loop_ref, nt_ref, loop_new, nt_new))
+    return known
 
 
 def jackknife_blocks(samples, n_blocks):

@@ -3,8 +3,11 @@ the fits after them), pinned without the paper's data (its figures are not
 available): closed forms, exact recovery of known parameters, identities of
 the jackknife, and the property the renormalisation exists for.
 
-The absolute sigma(T) values of the paper stay unpinned: they need its
-configurations.  What is pinned is the procedure."""
+The renormalisation procedure (seed from a short-distance match to a
+zero-temperature potential, transfer between couplings at equal
+temperature, fit of ln Z) is pinned by recovering a known Z(g^2) on
+synthetic data.  The absolute sigma(T) values of the paper stay unpinned:
+they need its configurations.  What is pinned is the procedure."""
 import json
 import os
 
@@ -138,3 +141,92 @@ def test_scan_string_tension_recovers_a_known_potential():
     conf, deconf = out[2.2], out[2.6]
     assert conf["rmax"] >= 4 and abs(conf["sigma"] - 0.12) < 4 * conf["sigma_err"] + 1e-3
     assert abs(deconf["sigma"]) < 4 * deconf["sigma_err"] + 1e-3
+
+
+def test_short_distance_seed_is_the_self_energy():
+    # bare free energy = renormalised zero-temperature potential + 2 ln Z at
+    # short distance, a finite-temperature deviation beyond r_max: the seed
+    # recovers ln Z and the per-r spread vanishes on the matched range
+    nt, ln_z = 6, 0.31
+    r = np.arange(1.0, 9.0)
+    v_ren = -0.25 / r + 0.05 * r
+    aF = v_ren + 2.0 * ln_z + np.where(r > 3, 0.01 * (r - 3) ** 2, 0.0)
+    corr = np.exp(-nt * aF)
+    got, spread = an.z_from_short_distance(r, corr, nt, v_ren, r_max=3)
+    assert got == pytest.approx(ln_z, abs=1e-14) and spread < 1e-14
+    # a wrong normalisation of the free energy (no 1/Nt) would not recover it
+    assert abs(np.mean((-np.log(corr) - v_ren)[:3]) / 2 - ln_z) > 0.5
+    with pytest.raises(ValueError):
+        an.z_from_short_distance(r, corr, nt, v_ren, r_max=0.5)
+
+
+def test_transfer_equalises_the_renormalised_loops():
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        ln_z_ref = rng.uniform(-0.5, 0.5)
+        nt_ref, nt_new = (int(v) for v in rng.choice([4, 6, 8, 10, 12], 2, replace=False))
+        l_ref, l_new = rng.uniform(0.01, 0.9, 2)
+        ln_z_new = an.z_transfer(ln_z_ref, l_ref, nt_ref, l_new, nt_new)
+        lhs = nt_ref * ln_z_ref + np.log(l_ref)
+        rhs = nt_new * ln_z_new + np.log(l_new)
+        assert lhs == pytest.approx(rhs, abs=1e-13)
+
+
+def test_renormalisation_chain_and_fit_recover_a_known_z():
+    # A synthetic world with a known Z(g^2) = exp(A g^2 + B g^4) (the
+    # paper's printed A, B), a lattice spacing a(g^2) = exp(-1/(2 b0 g^2))
+    # (SU(2) one-loop b0 = 11/(24 pi^2)), renormalised loops that depend on
+    # T = 1/(a Nt) alone, and bare loops L = L^r(T) / Z^Nt.  Seed at the
+    # first coupling from a potential match, then steps Nt = 4 -> 6 at equal
+    # T down a ladder of couplings; the fit of ln Z returns A and B.
+    A, B = GOLDEN["renormalisation_z"]["A"], GOLDEN["renormalisation_z"]["B"]
+    b0 = 11.0 / (24.0 * np.pi ** 2)
+
+    def ln_a(g2):
+        return -1.0 / (2.0 * b0 * g2)
+
+    def g2_of_ln_a(v):
+        return -1.0 / (2.0 * b0 * v)
+
+    def ln_z(g2):
+        return A * g2 + B * g2 * g2
+
+    def loop_ren(t):                       # any function of the temperature
+        return 0.6 * np.tanh(t / 3.0) + 0.05
+
+    def loop_bare(g2, nt):
+        t = 1.0 / (np.exp(ln_a(g2)) * nt)
+        return loop_ren(t) / np.exp(nt * ln_z(g2))
+
+    g2s = [1.25]
+    for _ in range(6):                     # a(g2_new) 6 = a(g2_ref) 4: same T
+        g2s.append(g2_of_ln_a(ln_a(g2s[-1]) + np.log(4.0 / 6.0)))
+    assert all(0.5 < g < 1.3 for g in g2s) and g2s == sorted(g2s, reverse=True)
+    # seed from a Cornell potential at the first coupling (Nt = 16, short r)
+    r = np.arange(1.0, 5.0)
+    v_ren = -0.26 / r + 0.04 * r
+    corr = np.exp(-16 * (v_ren + 2.0 * ln_z(g2s[0])))
+    seed_ln_z, _ = an.z_from_short_distance(r, corr, 16, v_ren, r_max=4)
+    steps = [(g2s[k], g2s[k + 1], loop_bare(g2s[k], 4), 4, loop_bare(g2s[k + 1], 6), 6) for k in range(6)]
+    known = an.renormalisation_chain((g2s[0], seed_ln_z), steps)
+    for g in g2s:
+        assert known[g] == pytest.approx(ln_z(g), abs=1e-12)
+    (fa, fb), cov, chi2 = an.fit_z(list(known), list(known.values()))
+    assert fa == pytest.approx(A, abs=1e-10) and fb == pytest.approx(B, abs=1e-10) and chi2 < 1e-20
+    # renormalised loops of one temperature now agree across Nt
+    for k in range(6):
+        lr4 = np.exp(4 * known[g2s[k]]) * loop_bare(g2s[k], 4)
+        lr6 = np.exp(6 * known[g2s[k + 1]]) * loop_bare(g2s[k + 1], 6)
+        assert lr4 == pytest.approx(lr6, rel=1e-12)
+    # a step whose reference coupling has no ln Z yet is refused
+    with pytest.raises(ValueError):
+        an.renormalisation_chain((g2s[0], seed_ln_z), steps[1:])
+    # with 0.1% noise on the bare loops the fit stays within its errors
+    rng = np.random.default_rng(11)
+    noisy = [(a_, b_, lr * (1 + 1e-3 * rng.normal()), n1, ln_ * (1 + 1e-3 * rng.normal()), n2)
+             for a_, b_, lr, n1, ln_, n2 in steps]
+    kn = an.renormalisation_chain((g2s[0], seed_ln_z), noisy)
+    # each step adds ~sqrt(2) 1e-3 / 6 to ln Z, accumulated along the chain
+    d = np.array([2.4e-4 * np.sqrt(k + 1e-9) + 1e-6 for k in range(len(g2s))])
+    (na, nb), ncov, _ = an.fit_z(list(kn), list(kn.values()), d)
+    assert abs(na - A) < 5 * np.sqrt(ncov[0, 0]) and abs(nb - B) < 5 * np.sqrt(ncov[1, 1])
