@@ -73,18 +73,20 @@ def parse():
     return ap.parse_args()
 
 
-SWEEP_SOURCES = ("su2_device.hpp", "su2_kernels.hip", "su2_launch.hpp", "su2_staged.hip", "su2_staged.hpp")
+SWEEP_SOURCES = ("su2_device.hpp", "su2_heatbath.hpp", "su2_kernels.hip", "su2_launch.hpp", "su2_staged.hip",
+                 "su2_staged.hpp", "../build.py")
 
 
 def csrc_sha256():
-    """Hash of the sources of the sweep and observable kernels, to tell
-    whether a stored counter profile is current."""
+    """Hash of the sources of the sweep and observable kernels and of the
+    build script (its flags), to tell whether a stored counter profile is
+    current."""
     import hashlib
     h = hashlib.sha256()
     try:
         for name in SWEEP_SOURCES:
             h.update(name.encode())
-            with open(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", name), "rb") as f:
+            with open(os.path.normpath(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", name)), "rb") as f:
                 h.update(f.read())
     except OSError:
         return None

@@ -90,7 +90,8 @@ typedef struct su2_lattice {
                             neighbourhood each block holds in LDS (where a
                             slab plan fits the lattice and the device's LDS;
                             not in a sweep that takes the plaquette), the
-                            other kernels the default strips */
+                            other kernels the default strips; -3 = staged
+                            as -2 for the heat-bath classes too */
     int32_t tile_y;      /* in strip order (tile >= 0): the update kernels
                             walk each column as tile_y ranges of Ny/tile_y
                             rows (tile_y must divide Ny; 0 = default);

@@ -66,8 +66,8 @@ int check_lattice_links(const su2_lattice_t *lat, su2::LaunchArgs *out)
         return fail(SU2_EINVAL, "lattice_id must be in [0, 2^27)");
     if (lat->tile > 0 && (lat->tile > lat->n[2] || lat->n[2] % lat->tile != 0))
         return fail(SU2_EINVAL, "a positive tile (strip width) must divide Nz");
-    if (lat->tile < -2)
-        return fail(SU2_EINVAL, "tile must be -2, -1, 0 or a divisor of Nz");
+    if (lat->tile < -3)
+        return fail(SU2_EINVAL, "tile must be -3, -2, -1, 0 or a divisor of Nz");
     if (lat->tile_y < 0 || (lat->tile_y > 0 && (lat->tile_y > lat->n[1] || lat->n[1] % lat->tile_y != 0)))
         return fail(SU2_EINVAL, "tile_y must be 0 or a divisor of Ny");
     if (!lat->links)

@@ -263,8 +263,8 @@ __host__ inline BlockOrder make_block_order(const int32_t n[4], int tile, int ti
     o.nz = (uint32_t)n[2];
     o.div_cols = make_fastdiv(o.cols);
     o.div_nt = make_fastdiv((uint32_t)n[3]);
-    // tile -2 (staged overrelaxation): the other kernels walk the default strips
-    const int w = (tile == 0 || tile == -2) ? default_strip(n) : tile;
+    // tiles -2 and -3 (staged updates): the other kernels walk the default strips
+    const int w = (tile == 0 || tile == -2 || tile == -3) ? default_strip(n) : tile;
     o.strip = w > 0 ? (uint32_t)w : 0u;
     o.div_w = make_fastdiv(w > 0 ? (uint32_t)w : 1u);
     // row ranges per column: tile_y > 0 as given (it divides Ny; the caller

@@ -82,13 +82,17 @@ bool launch_batch_sweep(const void *d_table, int count, int prec, uint32_t total
                         hipStream_t st);
 void launch_sweep_advance(uint32_t *d_sweep, hipStream_t st);
 void launch_overrelax(const LaunchArgs &a, int mu, int par, double *plaq_partials, hipStream_t st);
-// Walk value (descriptor field `tile`) of the LDS-staged overrelaxation:
-// classes whose lattice admits a slab plan run overrelax_staged_kernel, every
-// other kernel walks the default strips.
+// Walk values (descriptor field `tile`) of the LDS-staged updates: with -2
+// the overrelaxation classes whose lattice admits a slab plan run
+// overrelax_staged_kernel, with -3 the heat-bath classes too
+// (heatbath_staged_kernel); every other kernel walks the default strips.
 constexpr int kTileStaged = -2;
-// The LDS-staged overrelaxation of one class; false (nothing launched) if no
-// slab plan fits the lattice on the current device.
+constexpr int kTileStagedBoth = -3;
+// The LDS-staged overrelaxation / heat bath of one class; false (nothing
+// launched) if no slab plan fits the lattice on the current device.
 bool launch_overrelax_staged(const LaunchArgs &a, int mu, int par, hipStream_t st);
+bool launch_heatbath_staged(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, const uint32_t *d_sweep,
+                            int mu, int par, hipStream_t st);
 void launch_plaquette_sum(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 void launch_plaquette(const LaunchArgs &a, const WorkLayout &w, double *d_out, hipStream_t st);
 // The plaquette pass with its partials in the library's static scratch

@@ -11,6 +11,7 @@
 // its order, so the new links are bitwise those of the global-memory
 // kernel.
 #include "su2_device.hpp"
+#include "su2_heatbath.hpp"
 #include "su2_launch.hpp"
 #include "su2_staged.hpp"
 
@@ -198,6 +199,121 @@ __global__ __launch_bounds__(kStagedThreads) void overrelax_staged_kernel(Links<
     }
 }
 
+// One class (MU, par) of the heat bath, slab by slab: the slab walk, LDS
+// ring and register prefetch of the overrelaxation kernel above (without
+// the own link, which the heat bath does not read), and per slice the
+// sampling of su2_heatbath.hpp with the block's rejected lanes compacted
+// across all its threads.  The staple, the random words (keyed by the
+// site) and the sampling are those of the global-memory kernel, so the new
+// links are bitwise its links.
+template <class T, int MU>
+__global__ __launch_bounds__(kStagedThreads) void heatbath_staged_kernel(Links<T> U, Geom g, StagePlan p, int par,
+                                                                         double beta, uint32_t k0, uint32_t k1,
+                                                                         uint32_t c1, uint32_t sweep,
+                                                                         const uint32_t *d_sweep, uint32_t *flags)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    LdsLink<T> *lds = reinterpret_cast<LdsLink<T> *>(lds_raw);
+    __shared__ HbSharedT<kStagedThreads> sh;
+    const int opp = par ^ 1;
+    const uint32_t sw = d_sweep ? *d_sweep : sweep;
+
+    const uint32_t j = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t ia = j % p.na, ib = (j / p.na) % p.nb, is = j / (p.na * p.nb);
+    const uint32_t y0 = ia * p.A, b0 = ib * p.B;
+    const int32_t s0 = (int32_t)(is * p.S);
+    const uint32_t nx = (uint32_t)g.n[0];
+    const int32_t nsl = g.n[Roles<MU>::s];
+
+    stage_direct<T, MU>(U, g, p, lds, y0, b0, s0, 1u, s0 - 1, 0, opp);
+    stage_direct<T, MU>(U, g, p, lds, y0, b0, s0, 8u, 0, s0 - 1, opp);
+    stage_direct<T, MU>(U, g, p, lds, y0, b0, s0, 8u, 0, s0, opp);
+
+    const uint32_t sites = p.A * p.B * p.nxh;
+    const bool active = threadIdx.x < sites;
+    const uint32_t xh = threadIdx.x % p.nxh, row = threadIdx.x / p.nxh;
+    const int32_t a = (int32_t)(row % p.A), b = (int32_t)(row / p.A);
+    const uint32_t yb = y0 + (uint32_t)a + b0 + (uint32_t)b;
+    const uint32_t own_cb0 = xh + p.nxh * global_row_base<MU>(g, y0, b0, a, b);
+    uint32_t rowbase[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        rowbase[k] = staple_row_base<MU>(p, k, a, b);
+
+    constexpr int kPre = staged_prefetch(sizeof(T) * 4);
+    LoadBase lb[kPre];
+#pragma unroll
+    for (int r = 0; r < kPre; ++r) {
+        const uint32_t i = threadIdx.x + (uint32_t)r * kStagedThreads;
+        if (!(i < p.n_fresh && load_base<MU>(g, p, y0, b0, opp, i, lb[r])))
+            lb[r].info = 0xffffffffu;
+    }
+    // one slice of loads ahead: the sampler needs the registers a second
+    // buffer would take (with two, the FP32 kernel spills)
+    constexpr int kDepth = 1;
+    Quat<T> pre[kDepth][kPre];
+    auto prefetch = [&](int32_t sl, Quat<T>(&buf)[kPre]) {
+        const SliceTerms t = slice_terms<MU>(g, p, s0, sl);
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+            if (lb[r].info != 0xffffffffu) {
+                uint32_t cb, li;
+                load_at(lb[r], t, cb, li);
+                const int plane = (int)(lb[r].info & 0xffu);
+                buf[r] = U.ld(plane >> 1, plane & 1, cb);
+            }
+        }
+    };
+    const int32_t s_end = s0 + (int32_t)p.S;
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d)
+        if (s0 + d < s_end)
+            prefetch(s0 + d, pre[d]);
+
+    auto slice = [&](int32_t sl, int d) {
+        const SliceTerms t = slice_terms<MU>(g, p, s0, sl);
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+            if (lb[r].info != 0xffffffffu) {
+                uint32_t cb, li;
+                load_at(lb[r], t, cb, li);
+                lds[li] = {pre[d][r].w, pre[d][r].x, pre[d][r].y, pre[d][r].z};
+            }
+        }
+        __syncthreads();
+        if (sl + kDepth < s_end)
+            prefetch(sl + kDepth, pre[d]);
+        Quat<T> Vh = {1, 0, 0, 0};
+        double alpha = 0.0;
+        bool need = false;
+        uint32_t site = 0;
+        U32x4 r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0};
+        const uint32_t cb = own_cb0 + t.cb_s;
+        if (active) {
+            const uint32_t sc = (uint32_t)(sl < nsl ? sl : sl - nsl);
+            const uint32_t xs = 2u * xh + ((yb + sc + (uint32_t)par) & 1u);
+            const uint32_t xhv[3] = {shifted_xh(xs, -1, nx), xh, shifted_xh(xs, 1, nx)};
+            const Quat<T> V = staged_staple<T, MU>(p, lds, s0, sl, rowbase, xhv, par);
+            site = 2u * cb + (xs & 1u);
+            need = hb_staple_law<T>(V, beta, flags, Vh, alpha);
+            r0 = philox(site, c1, sw, 0u, k0, k1);
+            r1 = philox(site, c1, sw, 1u, k0, k1);
+        }
+        double x0 = 0.0, xlen = 0.0;
+        if (hb_sample<T, kStagedThreads>(need, alpha, site, r0, r1, c1, sw, k0, k1, flags, sh, x0, xlen)) {
+            const Quat<T> X = Direction<T>::make(x0, xlen, philox(site, c1, sw, 2u, k0, k1));
+            U.st(MU, par, cb, unitize(qmul_nd(X, Vh)));
+        }
+        __syncthreads();
+    };
+    for (int32_t sl = s0; sl < s_end; sl += kDepth) {
+#pragma unroll
+        for (int d = 0; d < kDepth; ++d)
+            if (sl + d < s_end)
+                slice(sl + d, d);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launcher.
 // ---------------------------------------------------------------------------
@@ -220,13 +336,16 @@ static uint32_t lds_per_block_limit()
     return cached[dev] > 0 ? (uint32_t)cached[dev] : 0u;
 }
 
+// static_lds: the kernel's own LDS besides the ring (the heat bath's
+// compaction state).
 template <int MU>
-static bool plan_for(const LaunchArgs &a, StagePlan &p)
+static bool plan_for(const LaunchArgs &a, uint32_t static_lds, StagePlan &p)
 {
     const uint32_t link_bytes = a.prec == kF32 ? 16u : 32u;
-    const uint32_t limit = lds_per_block_limit();
-    if (limit == 0)
+    const uint32_t device_limit = lds_per_block_limit();
+    if (device_limit <= static_lds)
         return false;
+    const uint32_t limit = device_limit - static_lds;
     // one slab per CU if the lattice allows it, else as many as it allows
     for (uint32_t min_blocks : {256u, 64u, 1u})
         if (make_stage_plan<MU>(a.n, link_bytes, limit, min_blocks, p))
@@ -238,7 +357,7 @@ template <class T, int MU>
 static bool launch_staged_or(const LaunchArgs &a, int par, hipStream_t st)
 {
     StagePlan p;
-    if (!plan_for<MU>(a, p))
+    if (!plan_for<MU>(a, 0u, p))
         return false;
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(a.links);
@@ -257,6 +376,43 @@ static bool launch_staged_or_t(const LaunchArgs &a, int mu, int par, hipStream_t
     case 2: return launch_staged_or<T, 2>(a, par, st);
     default: return launch_staged_or<T, 3>(a, par, st);
     }
+}
+
+template <class T, int MU>
+static bool launch_staged_hb(const LaunchArgs &a, int par, double beta, uint64_t seed, uint32_t sweep,
+                             const uint32_t *d_sweep, hipStream_t st)
+{
+    StagePlan p;
+    if (!plan_for<MU>(a, (uint32_t)sizeof(HbSharedT<kStagedThreads>), p))
+        return false;
+    Links<T> U;
+    U.p = reinterpret_cast<decltype(U.p)>(a.links);
+    U.half = (uint32_t)(a.volume / 2);
+    const Geom g = make_geom(a.n, 0, 0);
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    const uint32_t c1 = (uint32_t)MU + 4u * 1u + 16u * (uint32_t)a.lattice_id;
+    heatbath_staged_kernel<T, MU><<<p.na * p.nb * p.ns, kStagedThreads, p.lds_bytes, st>>>(
+        U, g, p, par, beta, k0, k1, c1, sweep, d_sweep, a.flags);
+    return true;
+}
+
+template <class T>
+static bool launch_staged_hb_t(const LaunchArgs &a, int mu, int par, double beta, uint64_t seed, uint32_t sweep,
+                               const uint32_t *d_sweep, hipStream_t st)
+{
+    switch (mu) {
+    case 0: return launch_staged_hb<T, 0>(a, par, beta, seed, sweep, d_sweep, st);
+    case 1: return launch_staged_hb<T, 1>(a, par, beta, seed, sweep, d_sweep, st);
+    case 2: return launch_staged_hb<T, 2>(a, par, beta, seed, sweep, d_sweep, st);
+    default: return launch_staged_hb<T, 3>(a, par, beta, seed, sweep, d_sweep, st);
+    }
+}
+
+bool launch_heatbath_staged(const LaunchArgs &a, double beta, uint64_t seed, uint32_t sweep, const uint32_t *d_sweep,
+                            int mu, int par, hipStream_t st)
+{
+    return a.prec == kF32 ? launch_staged_hb_t<float>(a, mu, par, beta, seed, sweep, d_sweep, st)
+                          : launch_staged_hb_t<double>(a, mu, par, beta, seed, sweep, d_sweep, st);
 }
 
 bool launch_overrelax_staged(const LaunchArgs &a, int mu, int par, hipStream_t st)

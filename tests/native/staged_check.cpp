@@ -170,7 +170,9 @@ static int check_shape(const int32_t n[4])
     // every plan the chooser could pick for a range of LDS limits and block
     // counts, plus hand-picked slabs
     int checked = 0;
-    const uint32_t limits[] = {16384, 49152, 65536, 131072, 163840};
+    // 147424: 160 KB less the staged heat bath's compaction state (512
+    // threads x 32 B + 32 B)
+    const uint32_t limits[] = {16384, 49152, 65536, 131072, 147424, 163840};
     const uint32_t mins[] = {1, 8, 64, 256};
     for (uint32_t lb : {16u, 32u})
         for (uint32_t lim : limits)
@@ -211,6 +213,14 @@ int main()
         if (make_stage_plan<3>(n, lb, 163840, 256, q)) {
             for (int par = 0; par < 2; ++par)
                 check_plan<3>(n, q, par);
+        }
+        // the staged heat bath's plans (its compaction state beside the ring)
+        for (int par = 0; par < 2; ++par) {
+            StagePlan h0, h3;
+            if (make_stage_plan<0>(n, lb, 147424, 256, h0))
+                check_plan<0>(n, h0, par);
+            if (make_stage_plan<3>(n, lb, 147424, 256, h3))
+                check_plan<3>(n, h3, par);
         }
         // a device that gives a block 64 KB
         StagePlan r;

@@ -114,7 +114,8 @@ def test_argument_checks_reject_before_any_hip_call(su2):
     assert L.su2_plaquette_noalloc(by(_desc(su2, n=(8, 7, 8, 8), work=0, wb=0)), 0x30000, s) == su2.SU2_EDIMS
     assert L.su2_get_flags(ok, None, s) == su2.SU2_EINVAL
     assert L.su2_get_flags(ok, 0x30002, s) == su2.SU2_EALIGN
-    # tile: a positive strip width must divide Nz
+    # tile: a positive strip width must divide Nz; -3 is the lowest walk
+    assert L.su2_init_cold(by(_desc(su2, tile=-4)), s) == su2.SU2_EINVAL
     assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 12, 8), tile=5)), s) == su2.SU2_EINVAL
     assert L.su2_init_cold(by(_desc(su2, n=(8, 8, 12, 8), tile=24)), s) == su2.SU2_EINVAL
     # tile_y: 0 or a divisor of Ny
