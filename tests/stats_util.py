@@ -1,13 +1,14 @@
 """Statistics used by the statistical pins and the FP32-versus-FP64 checks
 (test infrastructure: nothing here comes from the package under test).
 
-- blocking_error: the error of the mean of an autocorrelated series by
-  blocking (Flyvbjerg and Petersen, J. Chem. Phys. 91 (1989) 461): block
-  means over blocks of 2^l samples, the standard error of the mean at every
-  level that still has at least 32 blocks, and the largest of them (the
-  plateau for a series much longer than its autocorrelation time).  A
-  different method from the package's Gamma method, written separately;
-  pinned in tests/test_stats.py by the closed form for an AR(1) process.
+- gamma_error: the error of the mean of an autocorrelated series by the
+  Gamma method (U. Wolff, Comput. Phys. Commun. 156 (2004) 143): the
+  autocovariance summed up to a window W chosen automatically (the first W
+  at which exp(-W/tau) - tau/sqrt(W N) turns negative, tau the exponential
+  time implied by the running tau_int, S = 1.5), with the leading bias of
+  the mean's estimate removed.  Written here from the paper's definitions,
+  separately from the package's implementation; pinned in
+  tests/test_stats.py by the closed forms of an AR(1) process.
 - x0_cdf: the exact conditional distribution function of w0 = (1/2)Tr(W)
   when W has density ~ exp(alpha w0) with respect to Haar measure on SU(2),
   i.e. w0 has density ~ sqrt(1 - w0^2) exp(alpha w0) on [-1, 1].  Computed
@@ -20,25 +21,41 @@ import numpy as np
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(96)
 
 
-def blocking_error(a, min_blocks=32):
-    """Return (mean, error, tau_int, levels) of the series a by blocking;
-    tau_int = (error / naive error)^2 / 2, levels = the blocking levels used."""
+def gamma_error(a, S=1.5):
+    """Return (mean, error, tau_int, W) of the series a by the Gamma method."""
     a = np.asarray(a, dtype=np.float64)
-    mean = float(a.mean())
     n = a.size
+    mean = float(a.mean())
     if n < 2:
         return mean, 0.0, 0.5, 0
-    naive = float(a.std(ddof=1) / np.sqrt(n))
-    x = a.copy()
-    err = naive
-    level = 0
-    while x.size >= 2 * min_blocks:
-        m = x.size // 2
-        x = 0.5 * (x[:2 * m:2] + x[1:2 * m:2])
-        level += 1
-        err = max(err, float(x.std(ddof=1) / np.sqrt(x.size)))
-    tau = 0.5 * (err / naive) ** 2 if naive > 0 else 0.5
-    return mean, err, tau, level
+    d = a - mean
+    c0 = float(d @ d) / n
+    if not c0 > 0.0:
+        return mean, 0.0, 0.5, 0
+    # running sum of the normalised autocovariance, one lag at a time
+    total = c0                       # C(W) = Gamma(0) + 2 sum_{t<=W} Gamma(t)
+    cov = [c0]
+    w_end = n // 2
+    W = w_end
+    for t in range(1, w_end + 1):
+        g = float(d[:-t] @ d[t:]) / (n - t)
+        cov.append(g)
+        total += 2.0 * g
+        tau_int = total / (2.0 * c0)
+        if tau_int <= 0.5:           # no positive correlation left to sum
+            W = t
+            break
+        tau = S / np.log((2.0 * tau_int + 1.0) / (2.0 * tau_int - 1.0))
+        if np.exp(-t / tau) - tau / np.sqrt(t * n) < 0.0:
+            W = t
+            break
+    # the mean subtracted from the data lowers every Gamma(t) by C(W)/n to
+    # leading order: add it back, then sum again
+    cw = sum(cov[:W + 1]) * 2.0 - cov[0]
+    corrected = [g + cw / n for g in cov[:W + 1]]
+    cw = 2.0 * sum(corrected) - corrected[0]
+    tau_int = cw / (2.0 * corrected[0])
+    return mean, float(np.sqrt(max(cw, 0.0) / n)), float(tau_int), W
 
 
 def _x0_unnormalised(alpha, w):

@@ -159,23 +159,26 @@ def test_single_class_move_matches_oracle_fp32(su2):
 def test_learned_chain_is_exact(su2):
     # 16^3 x 4 at beta 2.3 (configs of the learned-proposal workload): plain
     # heat bath against heat bath + learned sweeps with an untrained,
-    # randomly perturbed network; Gamma-method errors, 3 sigma.
+    # randomly perturbed network; Gamma-method errors, 3 sigma.  |L| near
+    # beta_c decorrelates over ~200 heat-bath sweeps, so the chains run
+    # 16000 sweeps (~75 autocorrelation times) for its error to be reliable.
     from paper_1104_5432_amd import learned
     n, beta = (16, 16, 16, 4), 2.3
     params = torch.tensor(_params(40), dtype=torch.float32, device="cuda")
     res = {}
     for name, prm in (("hb", None), ("learned", params)):
+        print(f"learned-chain exactness: {name} chain", flush=True)
         lat = learned.thermalised_lattice(n, beta, 77, 100)
-        r = learned.run_chain(lat, beta, 77, 1500, params=prm, first_sweep=100)
+        r = learned.run_chain(lat, beta, 77, 16000, params=prm, first_sweep=100)
         res[name] = r
     assert 0.2 < res["learned"]["acceptance"] < 1.0
     for key in ("plaquette", "polyakov"):
-        a = np.array(res["hb"][key][200:])
-        b = np.array(res["learned"][key][200:])
+        a = np.array(res["hb"][key][1000:])
+        b = np.array(res["learned"][key][1000:])
         if key == "polyakov":
             a, b = np.abs(a), np.abs(b)
-        ma, ea, _, _ = stats_util.blocking_error(a)
-        mb, eb, _, _ = stats_util.blocking_error(b)
+        ma, ea, _, _ = stats_util.gamma_error(a)
+        mb, eb, _, _ = stats_util.gamma_error(b)
         z = (mb - ma) / np.hypot(ea, eb)
         print(f"{key}: hb {ma:.5f}({ea:.5f}) learned {mb:.5f}({eb:.5f}) z = {z:+.2f}", flush=True)
         assert abs(z) <= 3.0

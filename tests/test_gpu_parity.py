@@ -227,8 +227,8 @@ def test_paper_workload_plaquette_series(su2):
     pg = out[:, 0].cpu().numpy()
     pr = np.array(pr)
     assert _maxdiff(pg[:25], pr[:25]) <= 1e-12
-    mg, eg, _, _ = stats_util.blocking_error(pg[20:])
-    mr, er, _, _ = stats_util.blocking_error(pr[20:])
+    mg, eg, _, _ = stats_util.gamma_error(pg[20:])
+    mr, er, _, _ = stats_util.gamma_error(pr[20:])
     assert abs(mg - mr) <= 3 * np.hypot(eg, er)
     assert _flags(su2, lat) == 0
 
@@ -713,8 +713,8 @@ def test_fp32_ensemble_matches_fp64(su2, beta, n):
         assert _maxdiff((U * U).sum(-1), 1) <= (1e-14 if prec == "f64" else 1e-6)
         series[prec] = (out[therm:, 0].cpu().numpy(), np.abs(pol[therm:, 0].cpu().numpy()))
     for k, name in enumerate(("plaquette", "|L|")):
-        m64, e64, _, _ = stats_util.blocking_error(series["f64"][k])
-        m32, e32, _, _ = stats_util.blocking_error(series["f32"][k])
+        m64, e64, _, _ = stats_util.gamma_error(series["f64"][k])
+        m32, e32, _, _ = stats_util.gamma_error(series["f32"][k])
         z = (m32 - m64) / np.hypot(e64, e32)
         print(f"{name}: f64 {m64:.6f}({e64:.6f}) f32 {m32:.6f}({e32:.6f}) z = {z:+.2f}", flush=True)
         assert abs(z) <= 3.0

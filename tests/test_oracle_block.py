@@ -193,7 +193,7 @@ def test_block_move_samples_the_marginal():
     rate = acc / (3000 * 128)
     assert 0.05 < rate < 1.0, rate
     for j in range(len(cen)):
-        m, err, tau, _ = stats_util.blocking_error(np.array(series[j]))
+        m, err, tau, _ = stats_util.gamma_error(np.array(series[j]))
         assert abs(m - ref[j]) <= 4 * err + 1e-3, (j, m, ref[j], err, tau)
 
 

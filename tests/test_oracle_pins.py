@@ -521,12 +521,12 @@ def test_strong_coupling_plaquette(beta):
             series.append(p)
             planes.append(pl)
     u = special.iv(2, beta) / special.iv(1, beta)
-    mean, err, tau, _ = stats_util.blocking_error(series)
+    mean, err, tau, _ = stats_util.gamma_error(series)
     assert abs(mean - u) < 3 * err + 6 * u ** 5, (mean, u, err)
     # hypercubic symmetry: plane averages agree within errors
     planes = np.array(planes)
     pm = planes.mean(0)
-    pe = np.array([stats_util.blocking_error(planes[:, k])[1] for k in range(6)])
+    pe = np.array([stats_util.gamma_error(planes[:, k])[1] for k in range(6)])
     assert np.all(np.abs(pm - pm.mean()) < 4 * pe + 1e-12)
 
 
@@ -545,7 +545,7 @@ def test_weak_coupling_plaquette():
             oracle.overrelax_sweep(n, U)
             if s >= 20:
                 series.append(beta * (1.0 - oracle.plaquette(n, U)[0]))
-        m, err, _, _ = stats_util.blocking_error(series)
+        m, err, _, _ = stats_util.gamma_error(series)
         y.append(m)
         e.append(err)
     y, e = np.array(y), np.array(e)
