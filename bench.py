@@ -79,15 +79,19 @@ SWEEP_SOURCES = ("su2_device.hpp", "su2_heatbath.hpp", "su2_kernels.hip", "su2_l
 
 def csrc_sha256():
     """Hash of the sources of the sweep and observable kernels and of the
-    build script (its flags), to tell whether a stored counter profile is
-    current."""
+    build script (its flags), comments and blank lines left out, to tell
+    whether a stored counter profile was taken from the current code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     try:
         for name in SWEEP_SOURCES:
             h.update(name.encode())
-            with open(os.path.normpath(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", name)), "rb") as f:
-                h.update(f.read())
+            with open(os.path.normpath(os.path.join(ROOT, "paper_1104_5432_amd", "csrc", name))) as f:
+                text = f.read()
+            comment = r"#[^\n]*" if name.endswith(".py") else r"//[^\n]*"
+            code = [ln.rstrip() for ln in re.sub(comment, "", text).splitlines()]
+            h.update("\n".join(ln for ln in code if ln).encode())
     except OSError:
         return None
     return h.hexdigest()

@@ -792,7 +792,10 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, cons
 // FP64 5%; 96^4: 3%).  For small lattices, and the batched kernel over many
 // of them, the cap costs more latency hiding than it saves (a batch of
 // 0.1-2 M-site lattices: 10% slower), so it applies from 2^21 links per
-// class.  The cap is a static LDS reservation the kernel never touches:
+// class.  A waves-per-EU attribute cannot express it: that bounds the
+// compiler's register budget, not the residency, and with the 67-82 VGPRs
+// the kernel needs the hardware would still place 6 waves per SIMD.  The
+// cap is a static LDS reservation the kernel never touches:
 // kOrBlocksPerCu blocks of it fit the CU's kLdsPerCu bytes (gfx950: 160 KB),
 // one more does not.  (Requested as dynamic LDS of the same size at launch,
 // it held the kernel lower than 4 blocks per CU: FP64 class 556 us against
