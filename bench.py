@@ -73,8 +73,9 @@ def parse():
     return ap.parse_args()
 
 
-SWEEP_SOURCES = ("su2_device.hpp", "su2_heatbath.hpp", "su2_kernels.hip", "su2_launch.hpp", "su2_staged.hip",
-                 "su2_staged.hpp", "../build.py")
+# the sources of the global-memory update kernels, whose profiles give
+# `traffic` (the LDS-staged kernels, other walks, have none)
+SWEEP_SOURCES = ("su2_device.hpp", "su2_heatbath.hpp", "su2_kernels.hip", "su2_launch.hpp", "../build.py")
 
 
 def csrc_sha256():

@@ -88,6 +88,168 @@ __device__ __forceinline__ Quat<T> staged_staple(const StagePlan &p, const LdsLi
     return V;
 }
 
+// Terms FIRST .. FIRST + 2 of the staple's six (upper and lower of each
+// nu != MU in increasing nu: the order staged_staple adds them in), with
+// its products.
+template <class T, int MU, int FIRST>
+__device__ __forceinline__ void staged_terms(const StagePlan &p, const LdsLink<T> *lds, int32_t s0, int32_t sl,
+                                             const uint32_t (&rowbase)[4], const uint32_t (&xhv)[3], int par,
+                                             Quat<T> (&out)[3])
+{
+    using R = Roles<MU>;
+    using Ar = Arrays<MU>;
+    auto link = [&](int d, int32_t ex, int32_t ea, int32_t eb, int32_t es) -> Quat<T> {
+        const int k = Ar::array_of(d);
+        const int q = par ^ ((ex + ea + eb + es) & 1);
+        const uint32_t off = staple_shift(p, k, staple_slotq<MU>(k, sl + es, s0, q), ea, eb);
+        return from_lds(lds[rowbase[k] + off + xhv[ex + 1]]);
+    };
+    constexpr int32_t mx = R::slot(MU) == 0, ma = R::slot(MU) == 1, mb = R::slot(MU) == 2, ms = R::slot(MU) == 3;
+#pragma unroll
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == MU)
+            continue;
+        const int j = nu < MU ? nu : nu - 1; // position of nu among the three
+        const int sn = R::slot(nu);
+        const int32_t ex = sn == 0, ea = sn == 1, eb = sn == 2, es = sn == 3;
+        if (2 * j >= FIRST && 2 * j < FIRST + 3) {
+            const Quat<T> la = link(nu, mx, ma, mb, ms);
+            const Quat<T> lb = link(MU, ex, ea, eb, es);
+            const Quat<T> lc = link(nu, 0, 0, 0, 0);
+            out[2 * j - FIRST] = qmul_nd(qmul_nd(la, lb), lc);
+        }
+        if (2 * j + 1 >= FIRST && 2 * j + 1 < FIRST + 3) {
+            const Quat<T> ld = link(nu, mx - ex, ma - ea, mb - eb, ms - es);
+            const Quat<T> le = link(MU, -ex, -ea, -eb, -es);
+            const Quat<T> lf = link(nu, -ex, -ea, -eb, -es);
+            out[2 * j + 1 - FIRST] = qmul(qmul_dd(ld, le), lf);
+        }
+    }
+}
+
+// Two threads per site: the slab walk and LDS ring of overrelax_staged_kernel
+// below with 2 x sites threads, so that twice as many waves (4 per SIMD at
+// 512 sites) hide the memory latency of the slice being loaded.  The first
+// `sites` threads form staple terms 0-2 of their site, the second `sites`
+// threads terms 3-5, which they hand over through LDS (xch, after the
+// ring, term-major so that consecutive lanes touch consecutive links); the
+// first adds them in the same order, so the new link is bitwise
+// that of the one-thread kernel.  All threads share the loads of the next
+// slice; the first ones also hold their site's own link.
+template <class T, int MU>
+__global__ __launch_bounds__(kStagedPairThreads) void overrelax_staged2_kernel(Links<T> U, Geom g, StagePlan p,
+                                                                               int par, uint32_t *flags)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    LdsLink<T> *lds = reinterpret_cast<LdsLink<T> *>(lds_raw);
+    LdsLink<T> *xch = reinterpret_cast<LdsLink<T> *>(lds_raw + p.lds_bytes);
+    const int opp = par ^ 1;
+
+    const uint32_t j = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t ia = j % p.na, ib = (j / p.na) % p.nb, is = j / (p.na * p.nb);
+    const uint32_t y0 = ia * p.A, b0 = ib * p.B;
+    const int32_t s0 = (int32_t)(is * p.S);
+    const uint32_t nx = (uint32_t)g.n[0];
+    const int32_t nsl = g.n[Roles<MU>::s];
+
+    stage_direct<T, MU>(U, g, p, lds, y0, b0, s0, 1u, s0 - 1, 0, opp);
+    stage_direct<T, MU>(U, g, p, lds, y0, b0, s0, 8u, 0, s0 - 1, opp);
+    stage_direct<T, MU>(U, g, p, lds, y0, b0, s0, 8u, 0, s0, opp);
+
+    // the thread's site (blockDim.x = 2 x sites) and half of its staple
+    const uint32_t sites = p.A * p.B * p.nxh;
+    const bool second = threadIdx.x >= sites; // wave-uniform: sites is a multiple of 64
+    const uint32_t site_i = second ? threadIdx.x - sites : threadIdx.x;
+    const uint32_t xh = site_i % p.nxh, row = site_i / p.nxh;
+    const int32_t a = (int32_t)(row % p.A), b = (int32_t)(row / p.A);
+    const uint32_t yb = y0 + (uint32_t)a + b0 + (uint32_t)b;
+    const uint32_t own_cb0 = xh + p.nxh * global_row_base<MU>(g, y0, b0, a, b);
+    uint32_t rowbase[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        rowbase[k] = staple_row_base<MU>(p, k, a, b);
+
+    constexpr int kPre = kStagedPairPrefetch;
+    LoadBase lb[kPre];
+#pragma unroll
+    for (int r = 0; r < kPre; ++r) {
+        const uint32_t i = threadIdx.x + (uint32_t)r * blockDim.x;
+        if (!(i < p.n_fresh && load_base<MU>(g, p, y0, b0, opp, i, lb[r])))
+            lb[r].info = 0xffffffffu;
+    }
+    constexpr int kDepth = 2;
+    Quat<T> pre[kDepth][kPre];
+    Quat<T> pre_own[kDepth];
+    auto prefetch = [&](int32_t sl, Quat<T>(&buf)[kPre], Quat<T> &own_out) {
+        const SliceTerms t = slice_terms<MU>(g, p, s0, sl);
+        if (!second)
+            own_out = U.ld_nt(MU, par, own_cb0 + t.cb_s);
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+            if (lb[r].info != 0xffffffffu) {
+                uint32_t cb, li;
+                load_at(lb[r], t, cb, li);
+                const int plane = (int)(lb[r].info & 0xffu);
+                buf[r] = U.ld(plane >> 1, plane & 1, cb);
+            }
+        }
+    };
+    const int32_t s_end = s0 + (int32_t)p.S;
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) {
+        pre_own[d] = {1, 0, 0, 0};
+        if (s0 + d < s_end)
+            prefetch(s0 + d, pre[d], pre_own[d]);
+    }
+
+    auto slice = [&](int32_t sl, int d) {
+        const SliceTerms t = slice_terms<MU>(g, p, s0, sl);
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+            if (lb[r].info != 0xffffffffu) {
+                uint32_t cb, li;
+                load_at(lb[r], t, cb, li);
+                lds[li] = {pre[d][r].w, pre[d][r].x, pre[d][r].y, pre[d][r].z};
+            }
+        }
+        const Quat<T> own = pre_own[d];
+        __syncthreads();
+        if (sl + kDepth < s_end)
+            prefetch(sl + kDepth, pre[d], pre_own[d]);
+        const uint32_t sc = (uint32_t)(sl < nsl ? sl : sl - nsl);
+        const uint32_t xs = 2u * xh + ((yb + sc + (uint32_t)par) & 1u);
+        const uint32_t xhv[3] = {shifted_xh(xs, -1, nx), xh, shifted_xh(xs, 1, nx)};
+        Quat<T> term[3];
+        if (second) {
+            staged_terms<T, MU, 3>(p, lds, s0, sl, rowbase, xhv, par, term);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                xch[(uint32_t)k * sites + site_i] = {term[k].w, term[k].x, term[k].y, term[k].z};
+        } else {
+            staged_terms<T, MU, 0>(p, lds, s0, sl, rowbase, xhv, par, term);
+        }
+        __syncthreads();
+        if (!second) {
+            Quat<T> V = {0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                qacc(V, term[k]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                qacc(V, from_lds(xch[(uint32_t)k * sites + site_i]));
+            Quat<T> un;
+            if (overrelax_reflect(V, own, flags, un))
+                U.st(MU, par, own_cb0 + t.cb_s, un);
+        }
+    };
+    for (int32_t sl = s0; sl < s_end; sl += kDepth) {
+#pragma unroll
+        for (int d = 0; d < kDepth; ++d)
+            if (sl + d < s_end)
+                slice(sl + d, d);
+    }
+}
+
 // One class (MU, par) of overrelaxation, slab by slab.  Grid: one block per
 // slab (na x nb x ns), kStagedThreads threads, p.lds_bytes of dynamic LDS.
 template <class T, int MU>
@@ -356,13 +518,30 @@ static bool plan_for(const LaunchArgs &a, uint32_t static_lds, StagePlan &p)
 template <class T, int MU>
 static bool launch_staged_or(const LaunchArgs &a, int par, hipStream_t st)
 {
-    StagePlan p;
-    if (!plan_for<MU>(a, 0u, p))
-        return false;
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(a.links);
     U.half = (uint32_t)(a.volume / 2);
     const Geom g = make_geom(a.n, 0, 0);
+    // FP32: two threads per site where the ring and the hand-over area fit
+    // (the latter sized for the largest slab, 512 sites x 3 terms).  FP64
+    // keeps one thread per site: its ring leaves no room for the hand-over
+    // at the benchmarked sizes, and its loads would not fit 4 waves' registers.
+    if constexpr (sizeof(T) == 4) {
+        const uint32_t xch_max = 3u * 512u * (uint32_t)sizeof(LdsLink<T>);
+        StagePlan q;
+        if (plan_for<MU>(a, xch_max, q)) {
+            const uint32_t sites = q.A * q.B * q.nxh;
+            if (2u * sites <= (uint32_t)kStagedPairThreads && q.n_fresh <= 2u * sites * kStagedPairPrefetch) {
+                const uint32_t lds_bytes = q.lds_bytes + 3u * sites * (uint32_t)sizeof(LdsLink<T>);
+                overrelax_staged2_kernel<T, MU><<<q.na * q.nb * q.ns, 2u * sites, lds_bytes, st>>>(U, g, q, par,
+                                                                                                    a.flags);
+                return true;
+            }
+        }
+    }
+    StagePlan p;
+    if (!plan_for<MU>(a, 0u, p))
+        return false;
     overrelax_staged_kernel<T, MU><<<p.na * p.nb * p.ns, kStagedThreads, p.lds_bytes, st>>>(U, g, p, par, a.flags);
     return true;
 }

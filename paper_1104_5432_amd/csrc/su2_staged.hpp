@@ -19,6 +19,11 @@
 namespace su2 {
 
 constexpr int kStagedThreads = 512; // threads per block; at most one update per thread and slice
+// The two-threads-per-site overrelaxation: at most 2 x 512 threads, each
+// holding up to 5 links of the next slices' loads (the plan's at most
+// 512 x 10 links per slice).
+constexpr int kStagedPairThreads = 1024;
+constexpr int kStagedPairPrefetch = 5;
 
 // Next-slice links a thread holds in registers: 16-byte links 10, 32-byte 6.
 __host__ __device__ constexpr int staged_prefetch(uint32_t link_bytes)
