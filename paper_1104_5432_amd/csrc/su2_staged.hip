@@ -1,15 +1,16 @@
-// su2_staged.hip -- overrelaxation with the staple neighbourhood of a slab
-// staged in LDS (the slab plan and index arithmetic are in su2_staged.hpp).
+// su2_staged.hip -- the update kernels with the staple neighbourhood of a
+// slab staged in LDS (overrelaxation, with one or two threads per site, and
+// heat bath; the slab plan and index arithmetic are in su2_staged.hpp).
 // A block walks its slab slice by slice; for each slice it writes the
-// links it loaded two slices earlier (one in FP64) into LDS, issues the
-// loads of the slice after next (its share of the neighbourhood and each
-// thread's own link) into registers and then forms every staple of the
+// links it loaded one or two slices earlier into LDS, issues the loads of
+// a later slice (its share of the neighbourhood and, for overrelaxation,
+// each site's own link) into registers and then forms every staple of the
 // slice from LDS.  Each link of the class's neighbourhood is read from
 // memory once per slab (the halo rows once more by the neighbouring slab)
 // in contiguous 128-bit accesses along x: ~10 loads per update instead of
 // 19.  The staple is formed with the products and sums of staple_impl, in
-// its order, so the new links are bitwise those of the global-memory
-// kernel.
+// its order, and the heat bath samples with the code of su2_heatbath.hpp,
+// so the new links are bitwise those of the global-memory kernels.
 #include "su2_device.hpp"
 #include "su2_heatbath.hpp"
 #include "su2_launch.hpp"
