@@ -460,6 +460,19 @@ __device__ __forceinline__ Quat<float> unitize<float>(const Quat<float> &q)
     return {q.w * s, q.x * s, q.y * s, q.z * s};
 }
 
+// Counter arithmetic of the persistent sweep's grid-wide barrier: block b of
+// a grid of G blocks adds barrier_increment(b, G) to the counter word (the G
+// additions of one barrier sum to 2^31), and a block that read `old` from
+// its own addition has passed the barrier once bit 31 of the word differs.
+__host__ __device__ __forceinline__ uint32_t barrier_increment(uint32_t b, uint32_t g)
+{
+    return b == 0u ? 0x80000000u - (g - 1u) : 1u;
+}
+__host__ __device__ __forceinline__ bool barrier_passed(uint32_t now, uint32_t old)
+{
+    return ((now ^ old) & 0x80000000u) != 0u;
+}
+
 // XCD-aware block order: consecutive blocks are dispatched round-robin over
 // the 8 XCDs, each with its own L2; renumber so that each XCD works through
 // one contiguous range of tiles (neighbouring tiles share halo links).

@@ -281,12 +281,11 @@ __device__ __forceinline__ void grid_barrier(uint32_t *word, uint32_t spin_limit
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t inc = blockIdx.x == 0 ? 0x80000000u - (gridDim.x - 1u) : 1u;
+        const uint32_t inc = barrier_increment(blockIdx.x, gridDim.x);
         const uint32_t old = __hip_atomic_fetch_add(word, inc, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t polls = 0;
         bool flipped = false;
-        while (!(flipped = (((__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ^ old) &
-                              0x80000000u) != 0u)) &&
+        while (!(flipped = barrier_passed(__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), old)) &&
                ++polls < spin_limit)
             __builtin_amdgcn_s_sleep(4);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
