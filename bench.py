@@ -118,6 +118,18 @@ def profiled_traffic(kernel, prec, shape, walk):
     return None
 
 
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(shape, beta, seed, n_or, min_seconds=10.0):
     """The FP64 CPU oracle timed on a bounded sample of the same workload:
     whole steps (1 heat-bath + n_or overrelaxation sweeps + plaquette +
@@ -142,6 +154,7 @@ def cpu_baseline(shape, beta, seed, n_or, min_seconds=10.0):
         "value": updates / dt,
         "unit": "link updates/s",
         "cores": oracle.num_threads(),
+        "cpu": host_cpu_model(),
         "kind": "oracle",
         "sample": f"{'x'.join(map(str, n))} FP64 oracle, hot start, {steps} step(s) of 1 HB + {n_or} OR "
                   f"sweeps + plaquette + Polyakov/correlator, {dt:.1f} s wall",
@@ -440,7 +453,8 @@ def paper_workload(args):
                         "the mean plaquette each, lattices 8^4..64^4, FP32 and FP64; value: 64^4 FP32",
         },
         "by_size": rows,
-        "cpu_one_core": {"value": cpu_rate, "unit": "link updates/s", "cores": cpu_threads, "kind": "oracle",
+        "cpu_one_core": {"value": cpu_rate, "unit": "link updates/s", "cores": cpu_threads, "cpu": host_cpu_model(),
+                         "kind": "oracle",
                          "sample": f"16^4 FP64 oracle, 20 heat-bath iterations with the plaquette, {cpu_s:.1f} s"},
     }
     print(json.dumps(rec), flush=True)

@@ -41,4 +41,5 @@ def test_single_workload_line():
     assert roof["traffic"] is None          # no stored counters for this lattice and walk
     cpu = rec["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["value"] > 0 and cpu["cores"] >= 1 and cpu["sample"]
+    assert "cpu" in cpu                     # the host CPU model (None where unreadable)
 
