@@ -365,6 +365,8 @@ def su2_batch_sweep(batch, seed, sweep=0, d_sweep=None, n_or=4, spin_limit=0, st
     if d_sweep is not None:
         _tensor(d_sweep, batch.lattices[0], torch.int32, 1, "d_sweep")
     _tensor(batch.sync, batch.lattices[0], torch.int32, 1, "batch.sync")
+    if not 0 <= int(spin_limit) < (1 << 32):
+        raise ValueError("spin_limit must be in [0, 2^32)")
     _check(lib.su2_batch_sweep(batch.descs, batch.count, batch.table.data_ptr(), int(seed), int(sweep),
                                d_sweep.data_ptr() if d_sweep is not None else None, int(n_or),
                                batch.sync.data_ptr(), int(spin_limit), _stream(stream)))
