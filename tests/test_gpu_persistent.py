@@ -6,6 +6,7 @@ meeting at a grid-wide barrier between classes.
   then su2_batch_overrelax), for a mixed batch (ragged shapes, plain and
   column addressing) and for the temperature scan's shapes, where every
   block takes many items of each class; n_or = 0 too.
+- FP64 members match the oracle's heat-bath chain per link (1e-12).
 - The barrier word's low 31 bits are 0 after every call.
 - One captured launch (plus the sweep advance) per sweep replays bitwise
   like the eager class launches, replay after replay.
@@ -13,7 +14,10 @@ meeting at a grid-wide barrier between classes.
   launch still ends, every lattice carries SU2_FLAG_SYNC, and the barrier
   word is left consistent.
 """
+import numpy as np
 import pytest
+
+import oracle
 
 torch = pytest.importorskip("torch")
 
@@ -147,3 +151,27 @@ def test_persistent_sweep_gives_up_after_its_poll_limit(su2):
     for x, y in zip(fresh, ref):
         assert torch.equal(x.links, y.links), x.n
         assert _flags(su2, x) == 0
+
+
+def test_persistent_sweep_matches_oracle(su2):
+    # FP64, two members of different shapes, couplings and lattice ids,
+    # three persistent heat-bath sweeps (n_or = 0), per link against the
+    # oracle chain of each
+    seed = 1234
+    shapes, betas, ids = [(8, 8, 8, 8), (6, 4, 10, 8)], [2.3, 2.5], [3, 9]
+    print("persistent sweep against the oracle, f64", flush=True)
+    lats = [su2.Lattice(n, "f64", device="cuda", lattice_id=i) for n, i in zip(shapes, ids)]
+    refs = []
+    for lat, n, i in zip(lats, shapes, ids):
+        su2.su2_init_hot(lat, seed)
+        refs.append(oracle.init_hot(n, seed, lattice_id=i))
+    batch = su2.Batch(lats, betas)
+    for s in range(3):
+        su2.su2_batch_sweep(batch, seed, sweep=s, n_or=0)
+        for ref, n, beta, i in zip(refs, shapes, betas, ids):
+            assert oracle.heatbath_sweep(n, ref, beta, seed, s, lattice_id=i) == 0
+        _sync()
+        for lat, ref in zip(lats, refs):
+            err = float(np.max(np.abs(su2.to_canonical(lat).numpy() - ref)))
+            assert err <= 1e-12, (lat.n, s, err)
+    assert _low_bits_clear(batch)

@@ -135,3 +135,20 @@ def test_staged_heatbath_matches_oracle(su2):
     su2.su2_heatbath_sweep(lat, 2.3, 6, 0)
     torch.cuda.synchronize()
     assert float(np.max(np.abs(su2.to_canonical(lat).numpy() - U0))) <= 1e-12
+
+
+def test_staged_overrelax_bitwise_96(su2):
+    # the largest single lattice (5.4 GB of links, byte offsets beyond 4 GiB
+    # in the plane loads): a staged overrelaxation sweep equals the global
+    # kernel's bitwise
+    n = (96, 96, 96, 96)
+    print(f"staged overrelaxation {n} f32", flush=True)
+    staged = su2.Lattice(n, "f32", device="cuda", tile=-2)
+    plain = su2.Lattice(n, "f32", device="cuda", tile=96, tile_y=8)
+    su2.su2_init_cold(plain)
+    su2.su2_heatbath_sweep(plain, 2.5, 1234, 0)
+    staged.links.copy_(plain.links)
+    su2.su2_overrelax(staged, 1)
+    su2.su2_overrelax(plain, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(staged.links, plain.links)
