@@ -140,19 +140,32 @@ def test_block_sweep_matches_oracle(su2, n):
     assert int(f.item()) == 0
 
 
-def test_single_class_move_matches_oracle_fp32(su2):
-    n, beta, seed = (8, 8, 8, 2), 2.3, 12
+@pytest.mark.parametrize("seed,parity,colour", [(12, 1, 5), (13, 0, 2), (14, 1, 7), (15, 0, 0)])
+def test_single_class_move_matches_oracle_fp32(su2, seed, parity, colour):
+    # FP32 links against the FP64 oracle from the same (FP32-rounded) links:
+    # every moved link (a centre and its six redrawn neighbours, ~445 per
+    # class) agrees to the FP32 rounding of its staples (measured <= 3.2e-7),
+    # except that one centre's accept decision (and with it its block of 7
+    # links) may flip between FP32 and FP64 arithmetic on a near-tie; the
+    # accepted counts then differ by at most one.
+    n, beta = (8, 8, 8, 2), 2.3
     U = _config(n, beta, 10)
     lat = _lat(su2, n, "f32", U)
     U32 = su2.to_canonical(lat).numpy()
     y = np.zeros((n[3], n[2], n[1], n[0], 6))
     acc = torch.zeros(1, dtype=torch.int32, device="cuda")
-    su2.su2_lp_move(lat, beta, seed, 3, 1, 5, torch.zeros(lat.volume * 6, device="cuda"), acc)
+    su2.su2_lp_move(lat, beta, seed, 3, parity, colour, torch.zeros(lat.volume * 6, device="cuda"), acc)
     ref = U32.copy()
-    oracle.block_move(n, ref, beta, seed, 3, 1, 5, y)
+    f, accepted = oracle.block_move(n, ref, beta, seed, 3, parity, colour, y)
     _sync()
+    assert f == 0
+    moved = np.max(np.abs(U32 - ref), axis=-1) > 0
+    assert 400 < int(moved.sum()) <= 7 * 64
     d = np.max(np.abs(su2.to_canonical(lat).numpy() - ref), axis=-1)
-    assert np.mean(d > 1e-5) <= 0.01 and np.median(d) < 1e-6
+    big = d > 1e-5
+    assert int(big.sum()) <= 7, int(big.sum())
+    assert float(d[~big].max()) <= 2e-6, float(d[~big].max())
+    assert abs(int(acc.item()) - accepted) <= int(big.any())
 
 
 @pytest.mark.slow
