@@ -307,22 +307,23 @@ def test_fp32_heatbath_chain_matches_single_precision_oracle(su2, beta):
     # oracle's single-precision chain: with every decision taken in the same
     # precisions the chains stay together link by link.  A different
     # decision would move a link by O(0.1); the FP32 rounding differences
-    # (~5e-7 after one class) grow through the chain to ~1.5e-5 after three
-    # sweeps from the hot start, so the bound is 1e-4.
+    # grow through the chain (measured at beta 2.3: 3.1e-6, 7.1e-6, 1.5e-5
+    # after sweeps 1-3; at 6.0: 3.2e-6, 3.1e-6, 3.5e-6), held here to about
+    # 3x that, sweep by sweep.
     n, seed = (8, 8, 8, 8), 1234
     lat = _lat(su2, n, "f32")
     su2.su2_init_hot(lat, seed)
     _sync()
     ref = su2.to_canonical(lat).numpy()
-    for s in range(3):
+    for s, bound in zip(range(3), (1e-5, 2e-5, 4e-5)):
         for mu in range(4):
             for par in range(2):
                 assert oracle.heatbath_halfsweep_f32(n, ref, beta, seed, s, mu, par) == 0
         su2.su2_heatbath_sweep(lat, beta, seed, s)
-    _sync()
-    d = np.max(np.abs(su2.to_canonical(lat).numpy() - ref), axis=-1)
-    assert d.max() <= 1e-4, np.sort(d.ravel())[-3:]
-    assert np.median(d) <= 1e-6
+        _sync()
+        d = np.max(np.abs(su2.to_canonical(lat).numpy() - ref), axis=-1)
+        assert d.max() <= bound, (s, np.sort(d.ravel())[-3:])
+        assert np.median(d) <= 1e-6
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
