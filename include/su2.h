@@ -20,10 +20,15 @@
  *    checkerboard index cb = i/2 (a bijection within each parity).
  *  - A link U_mu(x) is the unit quaternion (a0,a1,a2,a3) of the SU(2)
  *    matrix a0 + i(a1 s1 + a2 s2 + a3 s3); mu = 0,1,2,3 = x,y,z,t.
- *  - Link layout in device memory (part of the ABI), plane q = 2*mu + parity:
- *      SU2_F32: float4 (a0,a1,a2,a3) at element q*(V/2) + cb;
- *      SU2_F64: double2 (a0,a1) at element (2q)*(V/2) + cb and
- *               double2 (a2,a3) at element (2q+1)*(V/2) + cb.
+ *  - Link layout in device memory (part of the ABI), plane q = 2*mu + parity,
+ *    in 16-byte elements, with S = su2_plane_stride(n, prec):
+ *      SU2_F32: float4 (a0,a1,a2,a3) at element q*S + cb;
+ *      SU2_F64: double2 (a0,a1) at element (2q)*S + cb and
+ *               double2 (a2,a3) at element (2q+1)*S + cb.
+ *    S = V/2, except for SU2_F64 with V/2 >= 2^18, where S = V/2 + 16392:
+ *    the sub-planes of large FP64 lattices are skewed by 256 KB + 128 B so
+ *    that equal cb in different sub-planes do not share L2 sets.  The
+ *    S - V/2 elements after each (sub-)plane are never read or written.
  *  - Random numbers: Philox4x32-10 with key (seed lo32, seed hi32) and
  *    counter (site i, mu + 4*kind + 16*lattice_id, sweep, 4*attempt + draw);
  *    kind 0 = hot start, 1 = heat bath.  A heat-bath sweep is therefore a
@@ -101,9 +106,16 @@ typedef struct su2_lattice {
     uint64_t work_bytes; /* size of work in bytes */
 } su2_lattice_t;
 
-/* Bytes of link storage: 4 V links of 16 (F32) or 32 (F64) bytes.
- * Returns 0 if the extents or precision are invalid. */
+/* Bytes of link storage: 8 planes (F32) or 16 sub-planes (F64) of
+ * su2_plane_stride() 16-byte elements each (4 V links of 16 or 32 bytes,
+ * plus the skew of large FP64 lattices).  Returns 0 if the extents or
+ * precision are invalid. */
 uint64_t su2_links_bytes(const int32_t n[4], int32_t prec);
+
+/* S of the link layout: 16-byte elements from the start of one plane (F32)
+ * or sub-plane (F64) to the next -- V/2, or V/2 + 16392 for SU2_F64 when
+ * V/2 >= 2^18.  Returns 0 if the extents or precision are invalid. */
+uint64_t su2_plane_stride(const int32_t n[4], int32_t prec);
 
 /* Bytes of workspace: flags word, reduction partials, Polyakov-loop field.
  * Returns 0 if the extents or precision are invalid. */

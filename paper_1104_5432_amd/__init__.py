@@ -51,6 +51,7 @@ _I4 = ctypes.POINTER(ctypes.c_int32)
 _VP = ctypes.c_void_p
 _SIGNATURES = {
     "su2_links_bytes": (ctypes.c_uint64, [_I4, ctypes.c_int32]),
+    "su2_plane_stride": (ctypes.c_uint64, [_I4, ctypes.c_int32]),
     "su2_workspace_bytes": (ctypes.c_uint64, [_I4, ctypes.c_int32]),
     "su2_init_cold": (ctypes.c_int, [_LP, _VP]),
     "su2_init_hot": (ctypes.c_int, [_LP, ctypes.c_uint64, _VP]),
@@ -120,6 +121,10 @@ def _dims(n):
 
 def su2_links_bytes(n, prec):
     return int(lib.su2_links_bytes(_dims(n)[1], _PRECS[prec]))
+
+
+def su2_plane_stride(n, prec):
+    return int(lib.su2_plane_stride(_dims(n)[1], _PRECS[prec]))
 
 
 def su2_workspace_bytes(n, prec):
@@ -499,10 +504,13 @@ def _site_tables(n, device):
 
 
 def _planes(lat):
+    # (sub-)planes `stride` elements apart; the elements past V/2 are skew
     half = lat.volume // 2
     if lat.prec == SU2_F32:
-        return lat.links.view(torch.float32).view(4, 2, half, 4)
-    return lat.links.view(torch.float64).view(4, 2, 2, half, 2)
+        stride = int(lib.su2_plane_stride(_dims(lat.n)[1], SU2_F32))
+        return lat.links.view(torch.float32).view(4, 2, stride, 4)[:, :, :half]
+    stride = int(lib.su2_plane_stride(_dims(lat.n)[1], SU2_F64))
+    return lat.links.view(torch.float64).view(4, 2, 2, stride, 2)[:, :, :, :half]
 
 
 def to_canonical(lat):

@@ -1,6 +1,7 @@
 // su2_api.cpp -- the C ABI declared in include/su2.h: argument checks (all
 // before any HIP call), workspace layout, launch sequencing, error codes.
 #include "su2.h"
+#include "su2_device.hpp"
 #include "su2_launch.hpp"
 #include "su2_learned.hpp"
 
@@ -46,10 +47,16 @@ bool aligned(const void *p, uintptr_t a)
     return ((uintptr_t)p % a) == 0;
 }
 
-uint64_t links_bytes_of(const int32_t n[4], int32_t prec)
+uint64_t plane_stride_of(const int32_t n[4], int32_t prec)
 {
     const uint64_t vol = (uint64_t)n[0] * n[1] * n[2] * n[3];
-    return vol * 4u * (prec == SU2_F32 ? 16u : 32u);
+    return su2::plane_stride((uint32_t)(vol / 2), prec == SU2_F64);
+}
+
+// 8 planes (F32) or 16 sub-planes (F64) of plane_stride_of 16-byte elements
+uint64_t links_bytes_of(const int32_t n[4], int32_t prec)
+{
+    return plane_stride_of(n, prec) * (prec == SU2_F32 ? 8u : 16u) * 16u;
 }
 
 // Checks of a lattice descriptor's extents, precision, id, walk and links;
@@ -249,6 +256,13 @@ uint64_t su2_links_bytes(const int32_t n[4], int32_t prec)
     if (!dims_ok(n) || !prec_ok(prec))
         return 0;
     return links_bytes_of(n, prec);
+}
+
+uint64_t su2_plane_stride(const int32_t n[4], int32_t prec)
+{
+    if (!dims_ok(n) || !prec_ok(prec))
+        return 0;
+    return plane_stride_of(n, prec);
 }
 
 uint64_t su2_workspace_bytes(const int32_t n[4], int32_t prec)

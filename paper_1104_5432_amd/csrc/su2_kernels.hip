@@ -216,7 +216,7 @@ __device__ __forceinline__ void heatbath_item(const BatchEntry &e, int par, uint
 {
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(e.links);
-    U.half = e.g.half;
+    U.stride = plane_stride(e.g.half, sizeof(T) == 8);
     const uint32_t c1 = (uint32_t)MU + 4u * 1u + e.lid16;
     if (e.col)
         heatbath_body<T, MU, true>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, item - e.block0, e.nblocks, sh);
@@ -229,7 +229,7 @@ __device__ __forceinline__ void overrelax_item(const BatchEntry &e, int par, uin
 {
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(e.links);
-    U.half = e.g.half;
+    U.stride = plane_stride(e.g.half, sizeof(T) == 8);
     if (e.col)
         overrelax_body<T, MU, true>(U, e.g, par, e.flags, item - e.block0, e.nblocks);
     else
@@ -394,7 +394,7 @@ static Links<T> links_of(const LaunchArgs &a)
 {
     Links<T> L;
     L.p = reinterpret_cast<decltype(L.p)>(a.links);
-    L.half = (uint32_t)(a.volume / 2);
+    L.stride = plane_stride((uint32_t)(a.volume / 2), sizeof(T) == 8);
     return L;
 }
 

@@ -725,7 +725,7 @@ static Links<T> links_of(const LaunchArgs &a)
 {
     Links<T> L;
     L.p = reinterpret_cast<decltype(L.p)>(a.links);
-    L.half = (uint32_t)(a.volume / 2);
+    L.stride = plane_stride((uint32_t)(a.volume / 2), sizeof(T) == 8);
     return L;
 }
 

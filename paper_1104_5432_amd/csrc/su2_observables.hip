@@ -15,7 +15,7 @@ static Links<T> links_of(const LaunchArgs &a)
 {
     Links<T> L;
     L.p = reinterpret_cast<decltype(L.p)>(a.links);
-    L.half = (uint32_t)(a.volume / 2);
+    L.stride = plane_stride((uint32_t)(a.volume / 2), sizeof(T) == 8);
     return L;
 }
 
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void polyakov_batch_kernel(const BatchEntry
     const BatchEntry &e = tab[find_entry_index<&BatchEntry::pblock0>(tab, count, blockIdx.x)];
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(e.links);
-    U.half = e.g.half;
+    U.stride = plane_stride(e.g.half, sizeof(T) == 8);
     polyakov_body<T>(U, e.g, e.lfield, e.poly_part, blockIdx.x - e.pblock0, e.pnblk);
 }
 

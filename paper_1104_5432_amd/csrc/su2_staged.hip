@@ -521,7 +521,7 @@ static bool launch_staged_or(const LaunchArgs &a, int par, hipStream_t st)
 {
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(a.links);
-    U.half = (uint32_t)(a.volume / 2);
+    U.stride = plane_stride((uint32_t)(a.volume / 2), sizeof(T) == 8);
     const Geom g = make_geom(a.n, 0, 0);
     // FP32: two threads per site where the ring and the hand-over area fit
     // (the latter sized for the largest slab, 512 sites x 3 terms).  FP64
@@ -567,7 +567,7 @@ static bool launch_staged_hb(const LaunchArgs &a, int par, double beta, uint64_t
         return false;
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(a.links);
-    U.half = (uint32_t)(a.volume / 2);
+    U.stride = plane_stride((uint32_t)(a.volume / 2), sizeof(T) == 8);
     const Geom g = make_geom(a.n, 0, 0);
     const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
     const uint32_t c1 = (uint32_t)MU + 4u * 1u + 16u * (uint32_t)a.lattice_id;

@@ -51,6 +51,22 @@ def test_sizes(su2):
     assert su2.su2_links_bytes((256, 256, 256, 254), "f32") > 0
 
 
+def test_plane_stride_and_skew(su2):
+    # S = V/2, except FP64 with V/2 >= 2^18: V/2 + 16392 (256 KB + 128 B);
+    # links bytes = 8 (F32) or 16 (F64) (sub-)planes of S 16-byte elements
+    for n in [(8, 8, 8, 8), (64, 64, 16, 6), (64, 64, 16, 8), (64, 64, 64, 64), (96, 96, 96, 96), (48, 48, 48, 6)]:
+        half = int(np.prod(n)) // 2
+        skew = 16392 if half >= 1 << 18 else 0
+        assert su2.su2_plane_stride(n, "f32") == half
+        assert su2.su2_plane_stride(n, "f64") == half + skew
+        assert su2.su2_links_bytes(n, "f32") == 8 * half * 16
+        assert su2.su2_links_bytes(n, "f64") == 16 * (half + skew) * 16
+    assert su2.su2_plane_stride((7, 8, 8, 8), "f64") == 0
+    assert su2.lib.su2_plane_stride((ctypes.c_int32 * 4)(8, 8, 8, 8), 5) == 0
+    # the largest volume: the skewed stride still fits the 32-bit element index
+    assert su2.su2_plane_stride((256, 256, 256, 254), "f64") == 2 ** 31 - 2 ** 24 + 16392
+
+
 def _desc(su2, n=(8, 8, 8, 8), prec=0, lid=0, links=0x10000000, work=0x20000000, wb=None, tile=0, tile_y=0):
     if wb is None:
         wb = su2.su2_workspace_bytes(n, 0) if all(v >= 2 and v % 2 == 0 for v in n) else 1 << 20
@@ -195,19 +211,42 @@ def test_layout_conversion_matches_documented_layout(su2, prec):
     back = su2.to_canonical(lat).numpy()
     tol = 0 if prec == "f64" else 6e-8
     assert np.max(np.abs(back - U)) <= tol
-    # the documented layout: plane q = 2 mu + parity, element cb = site / 2
-    nx, ny, nz, nt = n
-    half = int(np.prod(n)) // 2
-    for (x, y, z, t, mu) in [(1, 2, 0, 3, 2), (0, 0, 1, 7, 3), (3, 5, 1, 0, 0)]:
+    _check_documented_layout(su2, lat, U, [(1, 2, 0, 3, 2), (0, 0, 1, 7, 3), (3, 5, 1, 0, 0)], tol)
+
+
+def _check_documented_layout(su2, lat, U, points, tol):
+    # plane q = 2 mu + parity, element q*S + cb (F64: sub-planes 2q, 2q+1)
+    import torch
+    nx, ny, nz, nt = lat.n
+    S = su2.su2_plane_stride(lat.n, "f32" if lat.prec == su2.SU2_F32 else "f64")
+    for (x, y, z, t, mu) in points:
         site = x + nx * (y + ny * (z + nz * t))
         q = 2 * mu + (x + y + z + t) % 2
         cb = site // 2
-        if prec == "f32":
-            v = lat.links.view(torch.float32).view(-1, 4)[q * half + cb].double().numpy()
+        if lat.prec == su2.SU2_F32:
+            v = lat.links.view(torch.float32).view(-1, 4)[q * S + cb].double().numpy()
         else:
             d2 = lat.links.view(torch.float64).view(-1, 2)
-            v = np.concatenate([d2[(2 * q) * half + cb].numpy(), d2[(2 * q + 1) * half + cb].numpy()])
+            v = np.concatenate([d2[(2 * q) * S + cb].numpy(), d2[(2 * q + 1) * S + cb].numpy()])
         assert np.max(np.abs(v - U[t, z, y, x, mu])) <= tol
+
+
+def test_layout_conversion_of_a_skewed_fp64_lattice(su2):
+    # V/2 = 2^18: the sub-planes are 16392 elements apart beyond V/2; the
+    # conversion addresses them there and leaves the skew elements alone
+    import torch
+    import oracle
+    n = (64, 64, 16, 8)
+    half = int(np.prod(n)) // 2
+    U = oracle.init_hot(n, 11)
+    lat = su2.Lattice(n, "f64", device="cpu")
+    lat.links.fill_(0xA5)
+    su2.from_canonical(lat, U)
+    assert np.array_equal(su2.to_canonical(lat).numpy(), U)
+    d2 = lat.links.view(torch.float64).view(16, half + 16392, 2)
+    assert torch.equal(d2[:, half:].contiguous().view(torch.uint8).reshape(-1),
+                       torch.full((16 * 16392 * 16,), 0xA5, dtype=torch.uint8))
+    _check_documented_layout(su2, lat, U, [(1, 2, 0, 3, 2), (63, 63, 15, 7, 3), (2, 40, 9, 5, 0), (0, 0, 0, 0, 1)], 0)
 
 
 def test_batch_sweep_binding_refuses_host_lattices(su2):
