@@ -6,7 +6,8 @@ one with zeros, go through the same calls -- single-lattice updates on the
 strip, plain and LDS-staged walks, the sweeps and passes that take the
 plaquette and Polyakov loop, the batched and persistent sweeps, the learned
 block move -- and must give bitwise the same links and observables, with
-the NaN left where it was."""
+the NaN left where it was.  A skewed lattice of a shape that takes the
+kernels' coordinate addressing matches the oracle class by class."""
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -110,3 +111,30 @@ def test_skew_untouched_by_learned_block_move(su2):
     _same(su2, a, b)
     assert torch.equal(acc[0], acc[1]) and int(acc[0].item()) > 0
     _flags_clear(su2, a, b)
+
+
+@pytest.mark.parametrize("mu,par", [(0, 1), (3, 0)])
+def test_skewed_lattice_of_unaligned_shape_matches_oracle(su2, mu, par):
+    # 70 x 62 x 16 x 8: V/2 = 277760 (skewed) and columns of 2170 checkerboard
+    # sites, not a multiple of a wave, so the kernels take the coordinate
+    # path; one heat-bath class and one overrelaxation class per link
+    # against the oracle
+    import numpy as np
+    import oracle
+    n = (70, 62, 16, 8)
+    half = 70 * 62 * 16 * 8 // 2
+    assert su2.su2_plane_stride(n, "f64") == half + 16392
+    print(f"skewed FP64 layout, {n}, class ({mu},{par}) against the oracle", flush=True)
+    seed, beta = 515, 2.3
+    U = oracle.init_hot(n, seed)
+    lat = su2.Lattice(n, "f64", device="cuda")
+    su2.from_canonical(lat, U)
+    assert oracle.heatbath_halfsweep(n, U, beta, seed, 3, mu, par) == 0
+    su2.su2_heatbath_halfsweep(lat, beta, seed, 3, mu, par)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(su2.to_canonical(lat).numpy() - U)) <= 1e-13
+    oracle.overrelax_halfsweep(n, U, (mu + 1) % 4, 1 - par)
+    su2.su2_overrelax_halfsweep(lat, (mu + 1) % 4, 1 - par)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(su2.to_canonical(lat).numpy() - U)) <= 1e-13
+    _flags_clear(su2, lat)
