@@ -59,7 +59,9 @@ __device__ __forceinline__ void heatbath_body(const Links<T> &U, const Geom &g, 
     // and using them, while the loads are in flight (64^4 class: 213.5 ->
     // 208.7 us).  FP64 keeps the staple's interleaved loads and draws in the
     // order they are used: holding all 18 links would take 179 VGPRs and
-    // halve its occupancy.
+    // halve its occupancy, and drawing the words while only the first
+    // plane's six links are in flight (125 VGPRs, as now) made the 64^4
+    // class slower, 466 against 455 us.
     U32x4 r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0}, rdir = {0, 0, 0, 0};
     if (valid) {
         Quat<T> V;
