@@ -63,6 +63,7 @@ def test_plane_stride_and_skew(su2):
         assert su2.su2_links_bytes(n, "f64") == 16 * (half + skew) * 16
     assert su2.su2_plane_stride((7, 8, 8, 8), "f64") == 0
     assert su2.lib.su2_plane_stride((ctypes.c_int32 * 4)(8, 8, 8, 8), 5) == 0
+    assert su2.lib.su2_plane_stride(None, 0) == 0 and su2.lib.su2_links_bytes(None, 0) == 0
     # the largest volume: the skewed stride still fits the 32-bit element index
     assert su2.su2_plane_stride((256, 256, 256, 254), "f64") == 2 ** 31 - 2 ** 24 + 16392
 
