@@ -820,21 +820,23 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, cons
 // Residency cap of the overrelaxation kernel on large lattices.  At the 7
 // blocks per CU its registers allow, the blocks in flight on an XCD touch
 // more links than its 4 MB L2 holds and neighbours are evicted between uses;
-// 4 blocks per CU (16 waves) is faster for one large lattice (64^4: FP32 3%,
-// FP64 5%; 96^4: 3%).  For small lattices, and the batched kernel over many
-// of them, the cap costs more latency hiding than it saves (a batch of
-// 0.1-2 M-site lattices: 10% slower), so it applies from 2^21 links per
-// class.  A waves-per-EU attribute cannot express it: that bounds the
-// compiler's register budget, not the residency, and with the 67-82 VGPRs
-// the kernel needs the hardware would still place 6 waves per SIMD.  The
+// 3 blocks per CU (12 waves) is the fastest for one large lattice (64^4
+// class, FP32: 214.5 us at 3, 217.7 at 4, 246 at 2, ~227 uncapped; FP64:
+// 471 / 475 / 490 / 521 us; 96^4 FP32: 1215 us at 3, 1220 at 4).  For
+// small lattices, and the batched kernel over many of them, the cap costs
+// more latency hiding than it saves (a batch of 0.1-2 M-site lattices: 10%
+// slower), so it applies from 2^21 links per class.  A waves-per-EU
+// attribute cannot express it: that bounds the compiler's register budget,
+// not the residency, and with the 67-82 VGPRs the FP32 kernel needs the
+// hardware would still place 6 waves per SIMD.  The
 // cap is a static LDS reservation the kernel never touches:
 // kOrBlocksPerCu blocks of it fit the CU's kLdsPerCu bytes (gfx950: 160 KB),
 // one more does not.  (Requested as dynamic LDS of the same size at launch,
-// it held the kernel lower than 4 blocks per CU: FP64 class 556 us against
-// 487 us.)  The launcher checks once per device, with the occupancy query,
-// that the capped kernel runs exactly kOrBlocksPerCu blocks per CU, and
-// launches the uncapped one where it does not.
-constexpr int kOrBlocksPerCu = 4;
+// it held the kernel lower than the cap: FP64 class 556 us against 487 us
+// at a cap of 4.)  The launcher checks once per device, with the occupancy
+// query, that the capped kernel runs exactly kOrBlocksPerCu blocks per CU,
+// and launches the uncapped one where it does not.
+constexpr int kOrBlocksPerCu = 3;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kOrResidencyLds = kLdsPerCu / kOrBlocksPerCu - 4 * 1024;
 static_assert(kOrBlocksPerCu * kOrResidencyLds <= kLdsPerCu &&
