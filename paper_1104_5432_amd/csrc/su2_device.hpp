@@ -824,8 +824,9 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, cons
 // class, FP32: 214.5 us at 3, 217.7 at 4, 246 at 2, ~227 uncapped; FP64:
 // 471 / 475 / 490 / 521 us; 96^4 FP32: 1215 us at 3, 1220 at 4).  For
 // small lattices, and the batched kernel over many of them, the cap costs
-// more latency hiding than it saves (a batch of 0.1-2 M-site lattices: 10%
-// slower), so it applies from 2^21 links per class.  A waves-per-EU
+// more latency hiding than it saves (the batched overrelaxation of the
+// 16-lattice scan, 0.1-2 M sites each: 12% slower at 4 blocks per CU, 21%
+// at 3), so it applies from 2^21 links per class.  A waves-per-EU
 // attribute cannot express it: that bounds the compiler's register budget,
 // not the residency, and with the 67-82 VGPRs the FP32 kernel needs the
 // hardware would still place 6 waves per SIMD.  The
