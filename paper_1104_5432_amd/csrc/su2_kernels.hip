@@ -128,7 +128,8 @@ __device__ __forceinline__ Quat<T> overrelax_link(const Links<T> &U, const A &ad
     // scheduler it is sunk to its use after the staple algebra, which
     // exposes a second memory round trip per wave (64^4 class: 218.5 ->
     // 216.0 us).  FP64 keeps the sunk load: issued first, the FP64 class
-    // took 4.5% longer (485 -> 507 us) and fetched 6% more bytes beyond L2.
+    // took 4.5% longer (485 -> 507 us) and fetched 6% more bytes beyond L2
+    // (with skewed sub-planes and 3 blocks per CU: 473 -> 481 us).
     const uint32_t own = ad.at(0, 0, 0, 0);
     Quat<T> u;
     if constexpr (std::is_same<T, float>::value) {
