@@ -817,20 +817,22 @@ __device__ __forceinline__ Quat<T> staple(const Links<T> &U, const Geom &g, cons
     return staple<T, MU>(U, ad, par);
 }
 
-// Residency cap of the overrelaxation kernel on large lattices.  At the 7
+// Residency cap of the overrelaxation kernel on single lattices.  At the 7
 // blocks per CU its registers allow, the blocks in flight on an XCD touch
 // more links than its 4 MB L2 holds and neighbours are evicted between uses;
 // 3 blocks per CU (12 waves) is the fastest for one large lattice (64^4
 // class, FP32: 214.5 us at 3, 217.7 at 4, 246 at 2, ~227 uncapped; FP64:
-// 471 / 475 / 490 / 521 us; 96^4 FP32: 1215 us at 3, 1220 at 4).  For
-// small lattices, and the batched kernel over many of them, the cap costs
-// more latency hiding than it saves (the batched overrelaxation of the
-// 16-lattice scan, 0.1-2 M sites each: 12% slower at 4 blocks per CU, 21%
-// at 3), so it applies from 2^21 links per class.  A waves-per-EU
-// attribute cannot express it: that bounds the compiler's register budget,
-// not the residency, and with the 67-82 VGPRs the FP32 kernel needs the
-// hardware would still place 6 waves per SIMD.  The
-// cap is a static LDS reservation the kernel never touches:
+// 471 / 475 / 490 / 521 us; 96^4 FP32: 1215 us at 3, 1220 at 4), and so
+// it is for every single lattice measured down to 2^18 links per class
+// (64^3 x 8: 24.1 against 27.3 us uncapped; 32^4 and 48^3 x 6: 1.5%).
+// Below 2^17 links a class has at most two blocks per CU and the cap
+// changes nothing.  The batched kernel over many lattices stays uncapped:
+// there the cap costs more latency hiding than it saves (the 16-lattice
+// scan, 0.1-2 M sites each: 12% slower at 4 blocks per CU, 21% at 3).  A
+// waves-per-EU attribute cannot express the cap: that bounds the
+// compiler's register budget, not the residency, and with the 67-82 VGPRs
+// the FP32 kernel needs the hardware would still place 6 waves per SIMD.
+// The cap is a static LDS reservation the kernel never touches:
 // kOrBlocksPerCu blocks of it fit the CU's kLdsPerCu bytes (gfx950: 160 KB),
 // one more does not.  (Requested as dynamic LDS of the same size at launch,
 // it held the kernel lower than the cap: FP64 class 556 us against 487 us
@@ -846,7 +848,7 @@ static_assert(kOrBlocksPerCu * kOrResidencyLds <= kLdsPerCu &&
 
 __host__ inline bool residency_cap_pays(const Geom &g)
 {
-    return g.half >= (1u << 21);
+    return g.half >= (1u << 17);
 }
 
 __device__ __forceinline__ void reserve_lds_for_residency()
