@@ -240,7 +240,11 @@ int su2_batch_fill(const su2_lattice_t *lats, const double *betas, int32_t count
 int su2_batch_heatbath_sweep(const su2_lattice_t *lats, int32_t count, const void *d_table, uint64_t seed,
                              uint32_t sweep, const uint32_t *d_sweep, void *stream);
 
-/* n_sweeps overrelaxation sweeps of every lattice of the batch. */
+/* n_sweeps overrelaxation sweeps of every lattice of the batch.  Per class
+ * (mu, parity): one launch for the lattices of fewer than 2^20 sites, and
+ * for each larger lattice the class launch of su2_overrelax (whose residency
+ * cap the batched kernel cannot take), all on `stream`; every lattice's
+ * links are bitwise those of su2_overrelax on it alone. */
 int su2_batch_overrelax(const su2_lattice_t *lats, int32_t count, const void *d_table, int32_t n_sweeps,
                         void *stream);
 

@@ -506,6 +506,8 @@ int su2_batch_fill(const su2_lattice_t *lats, const double *betas, int32_t count
         o.nblocks = round8(su2::class_blocks(a));
         su2::fill_batch_entry(a, w, betas[j], o, static_cast<char *>(host_table) + j * su2::batch_entry_bytes());
         o.block0 += o.nblocks;
+        if (!su2::batch_own_launch(a.volume))
+            o.sub_block0 += o.nblocks;
         o.pblock0 += w.nblk_poly;
         o.cblock0 += w.nblk_corr * su2::corr_groups(w.rmax);
         o.ocol0 += 2u + (uint32_t)w.rmax;
@@ -570,10 +572,33 @@ int su2_batch_overrelax(const su2_lattice_t *lats, int32_t count, const void *d_
         return fail(SU2_EINVAL, "d_table must be an 8-byte aligned device pointer");
     if (n_sweeps < 0)
         return fail(SU2_EINVAL, "n_sweeps must be >= 0");
-    for (int s = 0; s < n_sweeps; ++s)
-        for (int mu = 0; mu < 4; ++mu)
-            for (int p = 0; p < 2; ++p)
-                su2::launch_overrelax_batch(d_table, count, lats[0].prec, total, mu, p, (hipStream_t)stream);
+    // lattices with launches of their own (batch_own_launch), and the
+    // batched grid of the others (the table's sub_block0 ranges)
+    std::vector<su2::LaunchArgs> own;
+    uint32_t batched = 0;
+    for (int j = 0; j < count; ++j) {
+        su2::LaunchArgs a;
+        check_lattice(&lats[j], &a, nullptr);
+        if (su2::batch_own_launch(a.volume))
+            own.push_back(a);
+        else
+            batched += round8(su2::class_blocks(a));
+    }
+    // Lattice by lattice: all sweeps of one large lattice before the next
+    // keep its links in the Infinity Cache between classes (the scan's five
+    // 64^3 x 8 lattices, 4 sweeps: 3.9 ms this way, 4.85 ms class by class
+    // across the lattices).  Lattices are independent, so only each
+    // lattice's own class order matters.
+    for (const su2::LaunchArgs &a : own)
+        for (int s = 0; s < n_sweeps; ++s)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int p = 0; p < 2; ++p)
+                    su2::launch_overrelax(a, mu, p, nullptr, (hipStream_t)stream);
+    if (batched)
+        for (int s = 0; s < n_sweeps; ++s)
+            for (int mu = 0; mu < 4; ++mu)
+                for (int p = 0; p < 2; ++p)
+                    su2::launch_overrelax_batch(d_table, count, lats[0].prec, batched, mu, p, (hipStream_t)stream);
     return launched();
 }
 

@@ -213,6 +213,10 @@ struct BatchEntry {
     uint32_t lid16;   // 16 * lattice_id, the lattice's share of counter word c1
     uint32_t block0;  // first block of this lattice in the batched grid (multiple of 8)
     uint32_t nblocks; // blocks of this lattice (multiple of 8)
+    // first block in the grid of the batched overrelaxation launches, which
+    // leave out the lattices that batch_own_launch gives launches of their
+    // own (their range there is empty: sub_block0 of the next lattice)
+    uint32_t sub_block0;
     uint32_t col;     // 1: the lattice qualifies for column addressing
     // Polyakov loop and correlator (the regions of the lattice's workspace
     // and the block counts its single-lattice launches use)
@@ -849,6 +853,25 @@ static_assert(kOrBlocksPerCu * kOrResidencyLds <= kLdsPerCu &&
 __host__ inline bool residency_cap_pays(const Geom &g)
 {
     return g.half >= (1u << 17);
+}
+
+// Lattices of a batch whose overrelaxation classes run as launches of their
+// own, lattice by lattice, rather than inside the batched launches.  All
+// classes of one such lattice run back to back, so its links stay in the
+// 256 MB Infinity Cache between them (a 64^3 x 8 FP32 lattice holds
+// 134 MB), where one launch per class over all lattices streams every
+// lattice through it; and a lattice alone takes the residency cap, which
+// slows the batched kernel (the 16-lattice scan: 21% at 3 blocks per CU).
+// The scan's five 64^3 x 8 lattices, 4 sweeps: 4.60 ms batched, 4.85 ms as
+// own launches class by class across the lattices, 3.91 ms lattice by
+// lattice.  From 2^19 links per class (2048 blocks, 8 per CU), where a
+// class is long enough to amortise its own launch.  (The heat bath stays
+// batched: lattice by lattice it made the scan 1.5% slower.)
+constexpr uint32_t kBatchOwnMinHalf = 1u << 19;
+
+__host__ inline bool batch_own_launch(uint64_t volume)
+{
+    return volume / 2 >= kBatchOwnMinHalf;
 }
 
 __device__ __forceinline__ void reserve_lds_for_residency()

@@ -202,43 +202,50 @@ __global__ __launch_bounds__(kBlock) void overrelax_kernel(Links<T> U, Geom g, i
     overrelax_body<T, MU, COL, PLAQ>(U, g, par, flags, blockIdx.x, gridDim.x, plaq_partials);
 }
 
-// The block's lattice: entries are ordered by block0 (strictly increasing,
-// entry 0 at block 0), so it is the last entry with block0 <= blockIdx.x.
-// One round of independent loads for up to 64 lattices instead of a chain
-// of dependent ones (which, exposed at low residency, cost more than the
-// update).
-__device__ __forceinline__ const BatchEntry &find_entry(const BatchEntry *tab, int count)
+// The lattice of block b of a batched grid: the entries' first blocks
+// (block0 over all lattices, sub_block0 over those without launches of
+// their own, where such a lattice has an empty range starting where the
+// next lattice's does) never decrease, so it is the last entry whose first
+// block is <= b.  One round of independent loads for up to 64 lattices
+// instead of a chain of dependent ones (which, exposed at low residency,
+// cost more than the update).
+template <uint32_t BatchEntry::*FIRST>
+__device__ __forceinline__ const BatchEntry &find_entry(const BatchEntry *tab, int count, uint32_t b)
 {
-    return tab[find_entry_index<&BatchEntry::block0>(tab, count, blockIdx.x)];
+    return tab[find_entry_index<FIRST>(tab, count, b)];
 }
 
-// Block `item` of a batched class launch (the lattice's blocks item - block0).
+// Block `rel` (0 .. e.nblocks - 1) of the lattice's heat-bath class.
 template <class T, int MU>
 __device__ __forceinline__ void heatbath_item(const BatchEntry &e, int par, uint32_t k0, uint32_t k1, uint32_t sw,
-                                              uint32_t item, HbShared &sh)
+                                              uint32_t rel, HbShared &sh)
 {
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(e.links);
     U.stride = plane_stride(e.g.half, sizeof(T) == 8);
     const uint32_t c1 = (uint32_t)MU + 4u * 1u + e.lid16;
     if (e.col)
-        heatbath_body<T, MU, true>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, item - e.block0, e.nblocks, sh);
+        heatbath_body<T, MU, true>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, rel, e.nblocks, sh);
     else
-        heatbath_body<T, MU, false>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, item - e.block0, e.nblocks, sh);
+        heatbath_body<T, MU, false>(U, e.g, par, e.beta, k0, k1, c1, sw, e.flags, rel, e.nblocks, sh);
 }
 
+// Block `rel` (0 .. e.nblocks - 1) of the lattice's overrelaxation class.
 template <class T, int MU>
-__device__ __forceinline__ void overrelax_item(const BatchEntry &e, int par, uint32_t item)
+__device__ __forceinline__ void overrelax_item(const BatchEntry &e, int par, uint32_t rel)
 {
     Links<T> U;
     U.p = reinterpret_cast<decltype(U.p)>(e.links);
     U.stride = plane_stride(e.g.half, sizeof(T) == 8);
     if (e.col)
-        overrelax_body<T, MU, true>(U, e.g, par, e.flags, item - e.block0, e.nblocks);
+        overrelax_body<T, MU, true>(U, e.g, par, e.flags, rel, e.nblocks);
     else
-        overrelax_body<T, MU, false>(U, e.g, par, e.flags, item - e.block0, e.nblocks);
+        overrelax_body<T, MU, false>(U, e.g, par, e.flags, rel, e.nblocks);
 }
 
+// A heat-bath class of every lattice of the batch (the grid of block0
+// ranges).  Unlike the overrelaxation it gains nothing from launches of its
+// own per large lattice (the scan: 1.5% slower that way).
 template <class T, int MU>
 __global__ __launch_bounds__(kBlock) void heatbath_batch_kernel(const BatchEntry *tab, int count, int par,
                                                                  uint32_t k0, uint32_t k1, uint32_t sweep,
@@ -246,13 +253,17 @@ __global__ __launch_bounds__(kBlock) void heatbath_batch_kernel(const BatchEntry
 {
     __shared__ HbShared sh;
     const uint32_t sw = d_sweep ? *d_sweep : sweep;
-    heatbath_item<T, MU>(find_entry(tab, count), par, k0, k1, sw, blockIdx.x, sh);
+    const BatchEntry &e = find_entry<&BatchEntry::block0>(tab, count, blockIdx.x);
+    heatbath_item<T, MU>(e, par, k0, k1, sw, blockIdx.x - e.block0, sh);
 }
 
+// An overrelaxation class of the batch's lattices without launches of
+// their own (those take the single-lattice kernel with its residency cap).
 template <class T, int MU>
 __global__ __launch_bounds__(kBlock) void overrelax_batch_kernel(const BatchEntry *tab, int count, int par)
 {
-    overrelax_item<T, MU>(find_entry(tab, count), par, blockIdx.x);
+    const BatchEntry &e = find_entry<&BatchEntry::sub_block0>(tab, count, blockIdx.x);
+    overrelax_item<T, MU>(e, par, blockIdx.x - e.sub_block0);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,11 +316,11 @@ __device__ __forceinline__ void batch_class_items(const BatchEntry *tab, int cou
                                                   uint32_t k0, uint32_t k1, uint32_t sw, HbShared &sh)
 {
     for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const BatchEntry &e = tab[find_entry_index<&BatchEntry::block0>(tab, count, item)];
+        const BatchEntry &e = find_entry<&BatchEntry::block0>(tab, count, item);
         if constexpr (HB)
-            heatbath_item<T, MU>(e, par, k0, k1, sw, item, sh);
+            heatbath_item<T, MU>(e, par, k0, k1, sw, item - e.block0, sh);
         else
-            overrelax_item<T, MU>(e, par, item);
+            overrelax_item<T, MU>(e, par, item - e.block0);
     }
 }
 
@@ -427,6 +438,7 @@ void fill_batch_entry(const LaunchArgs &a, const WorkLayout &w, double beta, con
     e.col = col_addressing_ok(e.g) ? 1u : 0u;
     e.block0 = o.block0;
     e.nblocks = o.nblocks;
+    e.sub_block0 = o.sub_block0;
     e.lfield = reinterpret_cast<double *>(a.work + w.off_lfield);
     e.poly_part = reinterpret_cast<double *>(a.work + w.off_poly);
     e.corr_part = reinterpret_cast<double *>(a.work + w.off_corr);

@@ -57,7 +57,7 @@ uint64_t batch_entry_bytes();
 // Polyakov blocks (pblock0), correlator blocks (cblock0) and output columns
 // of the batched Polyakov sums (ocol0); each the sum over earlier lattices.
 struct BatchOffsets {
-    uint32_t block0, nblocks, pblock0, cblock0, ocol0;
+    uint32_t block0, nblocks, sub_block0, pblock0, cblock0, ocol0;
 };
 void fill_batch_entry(const LaunchArgs &a, const WorkLayout &w, double beta, const BatchOffsets &o, void *dst);
 // Grid sizes of the batched Polyakov launches, from the same descriptors.

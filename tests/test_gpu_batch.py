@@ -4,7 +4,8 @@ captured-graph replay, through the C ABI.
 - A lattice updated inside a batch gives bit-identical links to the same
   lattice (same lattice_id, seed, beta) updated alone: the random numbers are
   keyed by (seed, sweep, site, mu, kind, lattice_id) and the update of a link
-  does not depend on which block or launch performs it.
+  does not depend on which block or launch performs it -- also for the
+  large lattices whose overrelaxation runs as launches of their own.
 - Batch members match the FP64 oracle per link (same bound as single runs).
 - The batched Polyakov loop and correlator are bitwise the per-lattice
   ones and leave the correlator rows beyond each lattice's range untouched.
@@ -57,6 +58,42 @@ def test_batch_matches_single_lattices(su2, prec):
         su2.su2_batch_heatbath_sweep(batch, seed, sweep=s)
         su2.su2_batch_overrelax(batch, 2)
         for lat, beta in zip(single, BETAS):
+            su2.su2_heatbath_sweep(lat, beta, seed, s)
+            su2.su2_overrelax(lat, 2)
+    _sync()
+    for a, b in zip(batched, single):
+        assert torch.equal(a.links, b.links), a.n
+        f = su2.su2_get_flags(a)
+        _sync()
+        assert int(f.item()) == 0
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_with_own_launch_lattices_matches_single_lattices(su2, prec):
+    # lattices of >= 2^20 sites run their overrelaxation classes as launches
+    # of their own (the capped single-lattice kernel), the others in the
+    # batched launch, whose table leaves them an empty range: large lattices
+    # first, between small ones and last, bitwise as each lattice alone
+    seed = 79
+    shapes = [(64, 64, 32, 8), (8, 8, 8, 4), (32, 32, 32, 32), (16, 16, 16, 4), (6, 4, 10, 8), (64, 64, 64, 4)]
+    betas = [2.3, 2.2, 2.5, 2.6, 0.5, 2.4]
+    print(f"batch with own-launch lattices, {prec}", flush=True)
+
+    def fresh():
+        out = []
+        for j, n in enumerate(shapes):
+            lat = su2.Lattice(n, prec, device="cuda", lattice_id=j)
+            su2.su2_init_hot(lat, seed)
+            out.append(lat)
+        return out
+
+    batched, single = fresh(), fresh()
+    assert sum(int(np.prod(n)) >= 1 << 20 for n in shapes) == 3
+    batch = su2.Batch(batched, betas)
+    for s in range(2):
+        su2.su2_batch_heatbath_sweep(batch, seed, sweep=s)
+        su2.su2_batch_overrelax(batch, 2)
+        for lat, beta in zip(single, betas):
             su2.su2_heatbath_sweep(lat, beta, seed, s)
             su2.su2_overrelax(lat, 2)
     _sync()
