@@ -104,6 +104,43 @@ def test_batch_with_own_launch_lattices_matches_single_lattices(su2, prec):
         assert int(f.item()) == 0
 
 
+def test_graph_replay_with_own_launch_lattices(su2):
+    # the large lattices' own overrelaxation launches inside a captured
+    # graph replay like the same calls made eagerly, replay after replay
+    seed, n_or, replays = 83, 2, 3
+    shapes = [(8, 8, 8, 4), (64, 64, 32, 8), (16, 16, 16, 4), (32, 32, 32, 32)]
+    betas = [2.2, 2.3, 2.6, 2.5]
+    print("graph replay with own-launch lattices", flush=True)
+
+    def fresh():
+        out = []
+        for j, n in enumerate(shapes):
+            lat = su2.Lattice(n, "f32", device="cuda", lattice_id=j)
+            su2.su2_init_hot(lat, seed)
+            out.append(lat)
+        return out
+
+    g_lats, e_lats = fresh(), fresh()
+    g_batch, e_batch = su2.Batch(g_lats, betas), su2.Batch(e_lats, betas)
+    d_sweep = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _sync()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        su2.su2_batch_heatbath_sweep(g_batch, seed, d_sweep=d_sweep)
+        su2.su2_batch_overrelax(g_batch, n_or)
+        su2.su2_sweep_advance(d_sweep)
+    _sync()
+    assert int(d_sweep.item()) == 0
+    for s in range(replays):
+        graph.replay()
+        su2.su2_batch_heatbath_sweep(e_batch, seed, sweep=s)
+        su2.su2_batch_overrelax(e_batch, n_or)
+        _sync()
+        assert int(d_sweep.item()) == s + 1
+        for a, b in zip(g_lats, e_lats):
+            assert torch.equal(a.links, b.links), (s, a.n)
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_batch_polyakov_matches_single_lattices(su2, prec):
     # su2_batch_polyakov: three launches for all lattices, bitwise the
